@@ -1,0 +1,211 @@
+"""Pins of the oracle's residual, smoothers and transfers (Secs. 2-5).
+
+Checks use invariants and special cases the paper's equations fix:
+free-stream preservation, discrete conservation in a closed box, exactness of
+the large-stencil reconstruction for quadratics, equality of multi-colour
+and sequential LU-SGS, the alpha -> 0 limits of the DF relaxation and of the
+DF prolongation, and the FAS identity (coarse RHS at W0 = restricted residual).
+"""
+import numpy as np
+import pytest
+
+import synthmesh as sm
+
+G = 1.4
+
+
+def cons_field(rho, u, v, p):
+    return np.stack([rho, rho * u, rho * v, p / (G - 1) + 0.5 * rho * (u * u + v * v)], axis=-1)
+
+
+def smooth_state(C, mach=0.5, amp=0.05):
+    x, y = C[:, 0], C[:, 1]
+    rho = 1.0 + amp * np.sin(0.7 * x + 0.3) * np.cos(0.5 * y)
+    u = mach * (1.0 + amp * np.cos(0.4 * y))
+    v = mach * amp * np.sin(0.6 * x)
+    p = 1.0 / G * (1.0 + amp * np.cos(0.3 * x - 0.2 * y))
+    return cons_field(rho, u, v, p)
+
+
+@pytest.fixture(scope="module")
+def ff_mesh():
+    return sm.annulus(12, 4, jitter=0.15, seed=3, nref=2, wall_tag=sm.FARFIELD)
+
+
+def test_free_stream_preservation(orc, ff_mesh):
+    o = orc.Oracle(ff_mesh, n_levels=3, mach=0.7, aoa_deg=10.0)
+    o.init_freestream()
+    W0, _, _ = o.get_state()
+    R, g, a = o.residual(0)
+    fg = o.face_geometry(0)
+    scale = fg["S"].max() * np.abs(W0).max()
+    assert np.abs(R).max() <= 1e-13 * scale
+    assert np.abs(g).max() <= 1e-12
+    assert (a == 1.0).all()
+    o.vcycle()
+    W1, _, _ = o.get_state()
+    assert np.abs(W1 - W0).max() <= 1e-13
+
+
+def test_closed_box_conserves_mass_and_energy(orc):
+    m = sm.structured_square(5, jitter=0.2, seed=4, tag=sm.SLIP)
+    for re in (0.0, 200.0):
+        o = orc.Oracle(m, n_levels=1, mach=0.5, reynolds=re)
+        V, C = o.cell_geometry(0)
+        o.set_state(smooth_state(C))
+        R, _, _ = o.residual(0)
+        # interior fluxes cancel pairwise and the slip walls carry no mass or energy
+        for q in (0, 3):
+            assert abs(R[:, q].sum()) <= 1e-14 * np.abs(R[:, q]).sum() + 1e-16
+
+
+def _tri_avg_quadratic(P, coef):
+    """Exact average over triangles of c0 + c1 x + c2 y + c3 x^2 + c4 xy + c5 y^2."""
+    x0, x1, x2 = P[:, 0, 0], P[:, 1, 0], P[:, 2, 0]
+    y0, y1, y2 = P[:, 0, 1], P[:, 1, 1], P[:, 2, 1]
+    ax, ay = (x0 + x1 + x2) / 3, (y0 + y1 + y2) / 3
+    axx = (x0 * x0 + x1 * x1 + x2 * x2 + x0 * x1 + x1 * x2 + x2 * x0) / 6
+    ayy = (y0 * y0 + y1 * y1 + y2 * y2 + y0 * y1 + y1 * y2 + y2 * y0) / 6
+    axy = (2 * (x0 * y0 + x1 * y1 + x2 * y2) + x0 * y1 + x1 * y0 + x1 * y2 + x2 * y1 + x2 * y0 + x0 * y2) / 12
+    c = coef
+    return c[0] + c[1] * ax + c[2] * ay + c[3] * axx + c[4] * axy + c[5] * ayy
+
+
+def test_large_stencil_reproduces_quadratics(orc):
+    """p^2 matches the neighbours' averages exactly and the slopes in the LS sense,
+    so a quadratic field is reproduced exactly (Sec. 3.1)."""
+    m = sm.annulus(12, 4, jitter=0.15, seed=9, nref=1, wall_tag=sm.FARFIELD)
+    o = orc.Oracle(m, n_levels=1, mach=0.3)
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(0)
+    coefs = [np.array([1.0, 0.01, -0.02, 0.003, 0.002, -0.001]),
+             np.array([0.3, 0.02, 0.01, -0.002, 0.001, 0.003]),
+             np.array([-0.1, 0.01, 0.02, 0.001, -0.003, 0.002]),
+             np.array([2.0, -0.03, 0.01, 0.002, 0.001, 0.004])]
+    P = m.coords[m.cells]
+    W = np.stack([_tri_avg_quadratic(P, c) for c in coefs], axis=1)
+    grad = np.zeros((m.n_cells, 4, 2))
+    for q, c in enumerate(coefs):
+        grad[:, q, 0] = c[1] + 2 * c[3] * C[:, 0] + c[4] * C[:, 1]
+        grad[:, q, 1] = c[2] + c[4] * C[:, 0] + 2 * c[5] * C[:, 1]
+    o.set_state(W, grad)
+    fg = o.face_geometry(0)
+    interior = np.bincount(fg["LR"][fg["LR"][:, 1] >= 0].ravel(), minlength=m.n_cells)
+    for i in rng.choice(np.where(interior == 3)[0], 25, replace=False):
+        for x in (C[i], P[i, 0] * 0.6 + 0.4 * C[i], P[i, 2]):
+            _, _, p2, _, _ = o.recon_eval(int(i), x)
+            exact = np.array([c[0] + c[1] * x[0] + c[2] * x[1] + c[3] * x[0] ** 2 + c[4] * x[0] * x[1]
+                              + c[5] * x[1] ** 2 for c in coefs])
+            np.testing.assert_allclose(p2, exact, rtol=0, atol=1e-11)
+
+
+def test_constant_data_reconstructs_constant(orc, ff_mesh):
+    o = orc.Oracle(ff_mesh, n_levels=1, mach=0.4)
+    o.init_freestream()
+    W, _, _ = o.get_state()
+    V, C = o.cell_geometry(0)
+    for i in (0, 17, 100):
+        Wx, gx, p2, p1, w = o.recon_eval(i, C[i] + 0.01)
+        np.testing.assert_allclose(Wx, W[i], rtol=1e-14)
+        assert np.abs(gx).max() <= 1e-12
+        np.testing.assert_allclose(w, 0.95, rtol=1e-15)
+
+
+def _prepared(orc, mesh, **kw):
+    o = orc.Oracle(mesh, n_levels=3, **kw)
+    V, C = o.cell_geometry(0)
+    o.set_state(smooth_state(C, mach=kw.get("mach", 0.5)))
+    return o
+
+
+def test_multicolour_lusgs_equals_sequential_lusgs(orc, small_mesh):
+    """Cells of one colour never interact, so Alg. 2 equals the classical sequential
+    LU-SGS in (colour, index) order, bit for bit (Sec. 4.2)."""
+    a = _prepared(orc, small_mesh, mach=0.5)
+    b = _prepared(orc, small_mesh, mach=0.5)
+    for o in (a, b):
+        o.smooth(0, 1)
+        o.restrict(0)
+    a.smooth(1, 3)
+    b.smooth_sequential(1, 3)
+    Wa = a.get_level_state(1)[0]
+    Wb = b.get_level_state(1)[0]
+    assert np.array_equal(Wa, Wb)
+    assert np.abs(Wa - a.get_level_state(1)[1]).max() > 0  # the sweep did something
+
+
+@pytest.fixture(scope="module")
+def small_mesh():
+    return sm.annulus(12, 4, jitter=0.15, seed=11, nref=2, wall_tag=sm.SLIP)
+
+
+def test_df_relaxation_zero_is_explicit_step(orc, small_mesh):
+    """alpha -> 0 turns the relaxed LU-SGS into the explicit step dW = dt/V * RHS (Sec. 4.3 remark)."""
+    o = _prepared(orc, small_mesh, mach=0.5)
+    o.smooth(0, 1)
+    o.restrict(0)
+    W, W0, F, a = o.get_level_state(1)
+    o.set_level_state(1, alpha=np.zeros_like(a))
+    R, _, _ = o.residual(1)
+    dte, _ = o.time_steps(1)
+    V, _ = o.cell_geometry(1)
+    o.smooth(1, 1)
+    W1 = o.get_level_state(1)[0]
+    np.testing.assert_allclose(W1 - W, (dte / V)[:, None] * (-R), rtol=1e-12, atol=1e-15)
+
+
+def test_restriction_and_fas_identities(orc, small_mesh):
+    o = _prepared(orc, small_mesh, mach=0.5)
+    o.smooth(0, 1)
+    Wf, _, _ = o.get_state()
+    Rf, _, af = o.residual(0)           # residual at the smoothed state
+    o.restrict(0)
+    W, W0, F, a1 = o.get_level_state(1)
+    V0, _ = o.cell_geometry(0)
+    V1, _ = o.cell_geometry(1)
+    p0 = small_mesh.parents[0]
+    for q in range(4):
+        assert (V1 * W0[:, q]).sum() == pytest.approx((V0 * Wf[:, q]).sum(), rel=1e-13)
+    np.testing.assert_allclose(a1, [af[p0 == I].min() for I in range(len(a1))])
+    # FAS: the coarse right-hand side at W0 is the restricted fine residual
+    Rc, _, _ = o.residual(1)
+    ref = np.stack([np.bincount(p0, weights=Rf[:, q]) for q in range(4)], axis=1)
+    np.testing.assert_allclose(Rc, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_restriction_of_constant_is_exact(orc, ff_mesh):
+    o = orc.Oracle(ff_mesh, n_levels=3, mach=0.6)
+    o.init_freestream()
+    W, _, _ = o.get_state()
+    o.restrict(0)
+    for l in (1, 2):
+        if l == 2:
+            o.restrict(1)
+        _, W0, _, _ = o.get_level_state(l)
+        np.testing.assert_allclose(W0, np.broadcast_to(W[0], W0.shape), rtol=1e-14)
+
+
+def test_df_prolongation_zero_is_identity(orc, small_mesh):
+    o = _prepared(orc, small_mesh, mach=0.5)
+    o.smooth(0, 1)
+    o.restrict(0)
+    o.smooth(1, 2)
+    W, g, a = o.get_state()
+    o.set_state(W, g, np.zeros_like(a))
+    o.prolong(0)
+    W2, _, _ = o.get_state()
+    assert np.array_equal(W, W2)
+    o.set_state(W, g, np.ones_like(a))
+    o.prolong(0)
+    W3, _, _ = o.get_state()
+    Wc, W0c, _, _ = o.get_level_state(1)
+    p0 = small_mesh.parents[0]
+    np.testing.assert_allclose(W3, W + (Wc - W0c)[p0], rtol=1e-14, atol=1e-15)
+
+
+def test_vcycle_is_stable_on_agglomerated_levels(orc):
+    m = sm.annulus(12, 4, jitter=0.1, seed=2, nref=2, wall_tag=sm.SLIP)
+    o = orc.Oracle(m, n_levels=3, use_parents=False, mach=0.4)
+    o.init_freestream()
+    norms = [o.vcycle() for _ in range(5)]
+    assert all(np.isfinite(norms)) and norms[-1] < norms[0]
