@@ -1,0 +1,215 @@
+/*
+ * cgks.h -- C ABI of the MI355X (gfx950) multigrid compact gas-kinetic
+ * scheme library (libcgks.so).
+ *
+ * The library computes the steady-state hot path of the geometric-multigrid
+ * compact gas-kinetic scheme (GMG-CGKS) on unstructured simplex meshes:
+ * one 3-level V-cycle made of
+ *   - the fine-level third-order CGKS residual: compact HWENO-type
+ *     reconstruction from cell averages and cell-averaged slopes (Sec. 3),
+ *     the time-dependent BGK interface flux at face Gauss points
+ *     (Sec. 2.3, Eqs. integral1, dis1, dis2), the direct evolution of the
+ *     cell-averaged slopes (Sec. 2.4) and the discontinuity-feedback (DF)
+ *     factor (Sec. 3.3);
+ *   - the explicit fine smoothing step (Sec. 5.2, Eq. smo);
+ *   - restriction of W and of the residual, the FAS forcing term, and the
+ *     DF-limited prolongation (Sec. 5.2, Eq. prolongation);
+ *   - on coarse levels, the first-order kinetic (KFVS) residual and the
+ *     multi-colour LU-SGS smoother with DF relaxation, swept one colour at a
+ *     time (Sec. 4, Alg. 1, Alg. 2, Eqs. gpu-forward-relaxation and
+ *     gpu-backward-relaxation).
+ *
+ * Conventions
+ *  - Non-dimensional free stream: rho = 1, p = 1/gamma (sound speed 1),
+ *    |u| = Mach, body diameter 1, mu_inf = Mach / Re.
+ *  - Conservative state W = (rho, rho u, rho v[, rho w], rho E); nvar = dim+2.
+ *  - Public arrays are in the mesh's original cell order ("original order")
+ *    and array-of-structures: W is [n_cells][nvar], gradW is
+ *    [n_cells][nvar][dim] (d W_q / d x_d), alpha is [n_cells].  The library
+ *    permutes internally (coarse levels are stored colour-contiguously).
+ *  - The residual R_i is the outward flux summed over the faces of cell i
+ *    (area- and time-averaged, not divided by the volume): the paper's
+ *    R^n times |Omega_i| (Sec. 2.2, Eq. high-order-flux-res).  The
+ *    multigrid "Res" of Sec. 5.2 is -R.
+ *  - Indices are 0-based except colours, which are 1..n_colors (Alg. 1).
+ *  - All work is ordered on the context's stream.  Calls that return data in
+ *    host memory synchronise that stream before returning.
+ *  - No result depends on thread scheduling: the library uses no
+ *    floating-point atomics; every reduction has a fixed order.
+ *
+ * Errors: every int-returning call returns CGKS_OK (0) on success, a
+ * negative CGKS_E* code on failure, or CGKS_NOTCONV (+1) from cgks_solve
+ * when max_cycles was reached.  cgks_last_error() gives a message owned by
+ * the context, valid until the next call on that context.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGKS_OK 0
+#define CGKS_NOTCONV 1
+#define CGKS_EINVAL (-1)   /* bad argument or call order */
+#define CGKS_EMESH (-2)    /* invalid mesh: non-positive volume, non-manifold face, untagged boundary */
+#define CGKS_EDEVICE (-3)  /* HIP runtime error; the message carries the hipError_t text */
+#define CGKS_ENONPHYS (-4) /* NaN, rho <= 0 or p <= 0 after a cycle; state rolled back */
+
+#define CGKS_HOST 0        /* pointer arguments are host memory */
+#define CGKS_DEVICE 1      /* pointer arguments are device memory of the context's device */
+
+#define CGKS_FP64 0        /* every step in FP64 */
+#define CGKS_MIXED 1       /* FP32 coarse-level correction inside FP64 defect correction */
+
+/* Boundary-face tags of the mesh input. */
+#define CGKS_TAG_FARFIELD 1   /* Riemann-invariant far field */
+#define CGKS_TAG_SLIP 2       /* inviscid slip wall (mirror state) */
+#define CGKS_TAG_ISOTHERMAL 3 /* no-slip wall at T = wall_T_ratio * T_inf */
+#define CGKS_TAG_ADIABATIC 4  /* no-slip adiabatic wall */
+
+/* Solver parameters.  cgks_default_params() fills the defaults below. */
+typedef struct cgks_params {
+    int dim;                   /* 2 (triangles) or 3 (tetrahedra) */
+    double gamma;              /* ratio of specific heats, default 1.4 */
+    double prandtl;            /* default 0.72, used when reynolds > 0 */
+    double mach;               /* free-stream Mach number */
+    double aoa_deg;            /* angle of attack in the x-y plane, degrees */
+    double reynolds;           /* Reynolds number per unit length; 0 => Euler */
+    double wall_T_ratio;       /* isothermal wall temperature / T_inf, default 1 */
+    double sutherland_S_ratio; /* Sutherland constant / T_inf, default 0.5 */
+    double cfl_exp;            /* explicit CFL of the fine step, default 0.5 */
+    double cfl_imp;            /* implicit CFL of the LU-SGS smoother, default 10 (Sec. 6) */
+    int n_levels;              /* multigrid levels, default 3 (Sec. 5.2) */
+    int n_pre_fine;            /* fine pre-smoothing steps, default 1 (Sec. 5.2) */
+    int n_post;                /* post-smoothing steps: only 0 is supported (Sec. 5.2) */
+    int n_sweeps;              /* LU-SGS iterations per coarse level, default 6 (Sec. 6.1) */
+    int df_relax;              /* 1: DF relaxation of LU-SGS (Sec. 4.3); 0: fully implicit */
+    int df_prolong;            /* 1: DF-limited prolongation (Eq. prolongation); 0: plain */
+    int precision;             /* CGKS_FP64 or CGKS_MIXED */
+    double tau_c1;             /* Euler collision time: tau = c1 dt + c2 |dp|/(pl+pr) dt */
+    double tau_c2;             /* default c1 = 0.01, c2 = 1 */
+    double weno_gamma_large;   /* linear weight of the large stencil, default 0.95 */
+    double weno_eps;           /* nonlinear-weight epsilon, default 1e-14 */
+    double lusgs_omega;        /* spectral-radius safety factor r >= |U.n| + c (Sec. 4.2), default 1 */
+    double skew_limit;         /* Alg. 3 minimum sin(skewness angle), default 0.2 */
+} cgks_params;
+
+/* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).
+ * Cells are simplices with positive orientation: triangles (dim=2) with
+ * counter-clockwise nodes, or tetrahedra (dim=3) with positive volume. */
+typedef struct cgks_mesh {
+    int dim;
+    int n_nodes;
+    const double* coords;      /* [n_nodes][dim] */
+    int n_cells;
+    const int32_t* cell_nodes; /* [n_cells][dim+1] */
+    int n_bfaces;
+    const int32_t* bface_nodes;/* [n_bfaces][dim], any node order */
+    const int32_t* bface_tag;  /* [n_bfaces], CGKS_TAG_* */
+} cgks_mesh;
+
+typedef struct cgks_ctx cgks_ctx;
+
+/* Fill *p with the defaults listed in cgks_params. */
+void cgks_default_params(cgks_params* p);
+
+/* Create a context on the current HIP device.  Returns CGKS_EINVAL for an
+ * unsupported dim / n_post, CGKS_EDEVICE if no device is usable. */
+int cgks_create(const cgks_params* p, cgks_ctx** out);
+
+/* Free every device and host resource of the context (NULL is ignored). */
+void cgks_destroy(cgks_ctx* c);
+
+/* Message of the last failing call on this context (owned by the context). */
+const char* cgks_last_error(const cgks_ctx* c);
+const char* cgks_strerror(int code);
+
+/* Borrow a HIP stream (a hipStream_t passed as void*); NULL selects the null
+ * stream.  The library never destroys it.  Invalidates captured graphs. */
+int cgks_set_stream(cgks_ctx* c, void* stream);
+
+/* Build the mesh hierarchy (Sec. 2.2 geometry, Sec. 3.1 reconstruction
+ * operators, Sec. 5.1 coarse geometry, Alg. 1 colouring of every level) and
+ * upload it to the device.  parent[l] (may be NULL) maps each cell of level l
+ * to its agglomerate on level l+1 for l = 0..n_levels-2; a NULL parent[l] or a
+ * NULL parent builds that level with Alg. 3 (cell coarsening).  CGKS_EMESH on
+ * an invalid mesh.  Host-side set-up; not on the timed path. */
+int cgks_mesh_setup(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* const* parent);
+
+/* Sizes of one level: cells and faces (coarse faces are agglomerate pairs). */
+int cgks_level_size(cgks_ctx* c, int level, int* n_cells, int* n_faces);
+
+/* Alg. 1 colours (1..n_colors) of a level in original order.  Host memory. */
+int cgks_coloring(cgks_ctx* c, int level, int32_t* color_out, int32_t* n_colors);
+
+/* Alg. 3 agglomeration of a level (independent of the hierarchy in use):
+ * agg_out[i] in 0..n_coarse-1, numbered by first appearance.  Host memory. */
+int cgks_agglomerate(cgks_ctx* c, int level, int32_t* agg_out, int32_t* n_coarse);
+
+/* Cell volumes and centroids of a level in original order (host memory). */
+int cgks_cell_geometry(cgks_ctx* c, int level, double* V, double* C);
+
+/* Free-stream initial state on every level: gradW = 0, alpha = 1. */
+int cgks_init_freestream(cgks_ctx* c);
+
+/* Fine-level state in/out.  mem = CGKS_HOST or CGKS_DEVICE.  gradW / alpha may
+ * be NULL (meaning 0 / 1 on input, not returned on output).  Device pointers
+ * are borrowed for the duration of the call. */
+int cgks_set_state(cgks_ctx* c, const double* W, const double* gradW, const double* alpha, int mem);
+int cgks_get_state(cgks_ctx* c, double* W, double* gradW, double* alpha, int mem);
+
+/* Coarse-level state (level >= 1): W, W0 (restricted state), F (FAS forcing),
+ * alpha (restricted DF).  Any pointer may be NULL.  Host memory. */
+int cgks_set_level_state(cgks_ctx* c, int level, const double* W, const double* W0,
+                         const double* F, const double* alpha);
+int cgks_get_level_state(cgks_ctx* c, int level, double* W, double* W0, double* F, double* alpha);
+
+/* Residual of a level at its current state.
+ * level 0: third-order CGKS residual R (n_cells x nvar), the DF-scaled
+ *   evolved slopes gradW_new (Sec. 2.4, Sec. 3.3) and the DF alpha_out.
+ * level >= 1: R = (outward KFVS flux sum) - F, so -R is the LU-SGS right-hand
+ *   side Res(W) + F (Sec. 5.2); gradW_new is ignored; alpha_out = level DF.
+ * The state is not modified.  Outputs may be NULL. */
+int cgks_residual(cgks_ctx* c, int level, double* R, double* gradW_new, double* alpha_out, int mem);
+
+/* Local time steps of a level (explicit and implicit CFL), original order. */
+int cgks_time_steps(cgks_ctx* c, int level, double* dt_exp, double* dt_imp);
+
+/* n smoothing iterations: level 0 explicit CGKS steps (Eq. smo); level >= 1
+ * multi-colour LU-SGS iterations with the level's forcing (Alg. 2). */
+int cgks_smooth(cgks_ctx* c, int level, int n);
+
+/* Restriction from level to level+1 (W volume-weighted, residual summed, DF
+ * minimum) followed by the FAS forcing F = Res* - Res(W0).  From level 0 it
+ * first evaluates the fine residual at the current state (its DF becomes the
+ * stored one). */
+int cgks_restrict(cgks_ctx* c, int level);
+
+/* DF-limited prolongation of the correction of level+1 onto level. */
+int cgks_prolong(cgks_ctx* c, int level);
+
+/* One V-cycle (n_pre_fine fine steps, restriction, n_sweeps LU-SGS on each
+ * coarse level, prolongation).  *norm_out (may be NULL) receives the
+ * free-stream-normalised RMS of R_rho / V at the start of the cycle.
+ * CGKS_ENONPHYS if the cycle produced NaN / non-positive density or pressure
+ * (the state is rolled back to the start of the cycle). */
+int cgks_vcycle(cgks_ctx* c, double* norm_out);
+
+/* V-cycles until norm <= tol or max_cycles.  history (may be NULL) receives
+ * up to history_cap norms.  Returns CGKS_OK, CGKS_NOTCONV or an error. */
+int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double* history,
+               int history_cap);
+
+/* Run n V-cycles with no host synchronisation between them (graph replay);
+ * the per-cycle norms stay on the device and are returned in history. */
+int cgks_run_cycles(cgks_ctx* c, int n, double* history);
+
+/* Counters: positivity-guard hits of the reconstruction, prolongation skips. */
+int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

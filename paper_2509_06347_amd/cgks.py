@@ -1,0 +1,274 @@
+"""ctypes binding of libcgks (argument marshalling only; see include/cgks.h).
+
+Function names follow the C ABI without the ``cgks_`` prefix on the
+:class:`Solver` methods.  Arrays may be numpy arrays (host memory) or torch
+tensors on the HIP device (device memory, passed as raw pointers).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libcgks.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
+                      "or python paper_2509_06347_amd/build.py (no CPU fallback exists)")
+
+_lib = C.CDLL(LIBPATH)
+
+OK, NOTCONV, EINVAL, EMESH, EDEVICE, ENONPHYS = 0, 1, -1, -2, -3, -4
+HOST, DEVICE = 0, 1
+FP64, MIXED = 0, 1
+TAG_FARFIELD, TAG_SLIP, TAG_ISOTHERMAL, TAG_ADIABATIC = 1, 2, 3, 4
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("gamma", C.c_double), ("prandtl", C.c_double),
+        ("mach", C.c_double), ("aoa_deg", C.c_double), ("reynolds", C.c_double),
+        ("wall_T_ratio", C.c_double), ("sutherland_S_ratio", C.c_double),
+        ("cfl_exp", C.c_double), ("cfl_imp", C.c_double), ("n_levels", C.c_int),
+        ("n_pre_fine", C.c_int), ("n_post", C.c_int), ("n_sweeps", C.c_int),
+        ("df_relax", C.c_int), ("df_prolong", C.c_int), ("precision", C.c_int),
+        ("tau_c1", C.c_double), ("tau_c2", C.c_double),
+        ("weno_gamma_large", C.c_double), ("weno_eps", C.c_double),
+        ("lusgs_omega", C.c_double), ("skew_limit", C.c_double),
+    ]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_nodes", C.c_int), ("coords", C.POINTER(C.c_double)),
+                ("n_cells", C.c_int), ("cell_nodes", C.POINTER(C.c_int32)),
+                ("n_bfaces", C.c_int), ("bface_nodes", C.POINTER(C.c_int32)),
+                ("bface_tag", C.POINTER(C.c_int32))]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int32)
+_sigs = {
+    "cgks_default_params": (None, [C.POINTER(Params)]),
+    "cgks_create": (C.c_int, [C.POINTER(Params), C.POINTER(_P)]),
+    "cgks_destroy": (None, [_P]),
+    "cgks_last_error": (C.c_char_p, [_P]),
+    "cgks_strerror": (C.c_char_p, [C.c_int]),
+    "cgks_set_stream": (C.c_int, [_P, _P]),
+    "cgks_mesh_setup": (C.c_int, [_P, C.POINTER(Mesh), C.c_int, C.POINTER(_I)]),
+    "cgks_level_size": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cgks_coloring": (C.c_int, [_P, C.c_int, _I, _I]),
+    "cgks_agglomerate": (C.c_int, [_P, C.c_int, _I, _I]),
+    "cgks_cell_geometry": (C.c_int, [_P, C.c_int, _D, _D]),
+    "cgks_init_freestream": (C.c_int, [_P]),
+    "cgks_set_state": (C.c_int, [_P, _P, _P, _P, C.c_int]),
+    "cgks_get_state": (C.c_int, [_P, _P, _P, _P, C.c_int]),
+    "cgks_set_level_state": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
+    "cgks_get_level_state": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
+    "cgks_residual": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
+    "cgks_time_steps": (C.c_int, [_P, C.c_int, _P, _P]),
+    "cgks_smooth": (C.c_int, [_P, C.c_int, C.c_int]),
+    "cgks_restrict": (C.c_int, [_P, C.c_int]),
+    "cgks_prolong": (C.c_int, [_P, C.c_int]),
+    "cgks_vcycle": (C.c_int, [_P, _D]),
+    "cgks_solve": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), _D, C.c_int]),
+    "cgks_run_cycles": (C.c_int, [_P, C.c_int, _D]),
+    "cgks_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTS = tuple(_sigs)
+
+
+class CgksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.cgks_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def default_params(**kw):
+    p = Params()
+    _lib.cgks_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(a):
+    """Raw pointer and memory kind of a numpy array or a device tensor (None -> NULL)."""
+    if a is None:
+        return None, HOST
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, HOST
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), (DEVICE if a.is_cuda else HOST)
+    raise TypeError(type(a))
+
+
+class Solver:
+    """One solver context on one mesh (see include/cgks.h)."""
+
+    def __init__(self, mesh, n_levels=3, use_parents=True, stream=None, **params):
+        params.setdefault("dim", mesh.dim)
+        params.setdefault("n_levels", n_levels)
+        self.params = default_params(**params)
+        self.dim = mesh.dim
+        self.nvar = mesh.dim + 2
+        ctx = _P()
+        rc = _lib.cgks_create(C.byref(self.params), C.byref(ctx))
+        if rc != OK:
+            raise CgksError(rc, "cgks_create")
+        self.ctx = ctx
+        if stream is not None:
+            self._check(_lib.cgks_set_stream(self.ctx, _P(stream)))
+        keep = [np.ascontiguousarray(mesh.coords, dtype=np.float64),
+                np.ascontiguousarray(mesh.cells, dtype=np.int32),
+                np.ascontiguousarray(mesh.bfaces, dtype=np.int32),
+                np.ascontiguousarray(mesh.btags, dtype=np.int32)]
+        m = Mesh(mesh.dim, mesh.n_nodes, keep[0].ctypes.data_as(_D), mesh.n_cells,
+                 keep[1].ctypes.data_as(_I), len(keep[3]), keep[2].ctypes.data_as(_I),
+                 keep[3].ctypes.data_as(_I))
+        par = (_I * max(n_levels - 1, 1))()
+        for l in range(n_levels - 1):
+            if use_parents and l < len(mesh.parents):
+                a = np.ascontiguousarray(mesh.parents[l], dtype=np.int32)
+                keep.append(a)
+                par[l] = a.ctypes.data_as(_I)
+            else:
+                par[l] = _I()
+        self._check(_lib.cgks_mesh_setup(self.ctx, C.byref(m), n_levels, par))
+        self.n_levels = n_levels
+        self.sizes = []
+        for l in range(n_levels):
+            nc, nf = C.c_int(), C.c_int()
+            self._check(_lib.cgks_level_size(self.ctx, l, C.byref(nc), C.byref(nf)))
+            self.sizes.append((nc.value, nf.value))
+
+    def _check(self, rc):
+        if rc < 0:
+            raise CgksError(rc, _lib.cgks_last_error(self.ctx).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.cgks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # set-up queries ----------------------------------------------------------
+    def coloring(self, level):
+        n = self.sizes[level][0]
+        col = np.zeros(n, dtype=np.int32)
+        nc = C.c_int32()
+        self._check(_lib.cgks_coloring(self.ctx, level, col.ctypes.data_as(_I), C.byref(nc)))
+        return col, nc.value
+
+    def agglomerate(self, level=0):
+        n = self.sizes[level][0]
+        agg = np.zeros(n, dtype=np.int32)
+        nc = C.c_int32()
+        self._check(_lib.cgks_agglomerate(self.ctx, level, agg.ctypes.data_as(_I), C.byref(nc)))
+        return agg, nc.value
+
+    def cell_geometry(self, level=0):
+        n = self.sizes[level][0]
+        V, Cc = np.zeros(n), np.zeros((n, self.dim))
+        self._check(_lib.cgks_cell_geometry(self.ctx, level, V.ctypes.data_as(_D), Cc.ctypes.data_as(_D)))
+        return V, Cc
+
+    # state -------------------------------------------------------------------
+    def init_freestream(self):
+        self._check(_lib.cgks_init_freestream(self.ctx))
+
+    def set_state(self, W, grad=None, alpha=None):
+        arrs = [W, grad, alpha]
+        if isinstance(W, np.ndarray):
+            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in arrs]
+        ptrs = [_ptr(a) for a in arrs]
+        mem = ptrs[0][1]
+        self._check(_lib.cgks_set_state(self.ctx, ptrs[0][0], ptrs[1][0], ptrs[2][0], mem))
+
+    def get_state(self):
+        n = self.sizes[0][0]
+        W = np.zeros((n, self.nvar))
+        g = np.zeros((n, self.nvar, self.dim))
+        a = np.zeros(n)
+        self._check(_lib.cgks_get_state(self.ctx, W.ctypes.data, g.ctypes.data, a.ctypes.data, HOST))
+        return W, g, a
+
+    def get_state_into(self, W, grad=None, alpha=None):
+        """Write the fine state into caller-provided arrays / device tensors."""
+        p = [_ptr(x) for x in (W, grad, alpha)]
+        self._check(_lib.cgks_get_state(self.ctx, p[0][0], p[1][0], p[2][0], p[0][1]))
+
+    def set_level_state(self, level, W=None, W0=None, F=None, alpha=None):
+        arrs = [None if x is None else np.ascontiguousarray(x, dtype=np.float64) for x in (W, W0, F, alpha)]
+        self._check(_lib.cgks_set_level_state(self.ctx, level, *[None if a is None else a.ctypes.data for a in arrs]))
+
+    def get_level_state(self, level):
+        n = self.sizes[level][0]
+        W, W0, F = (np.zeros((n, self.nvar)) for _ in range(3))
+        a = np.zeros(n)
+        self._check(_lib.cgks_get_level_state(self.ctx, level, W.ctypes.data, W0.ctypes.data,
+                                              F.ctypes.data, a.ctypes.data))
+        return W, W0, F, a
+
+    # solver ------------------------------------------------------------------
+    def residual(self, level=0):
+        n = self.sizes[level][0]
+        R = np.zeros((n, self.nvar))
+        g = np.zeros((n, self.nvar, self.dim))
+        a = np.zeros(n)
+        self._check(_lib.cgks_residual(self.ctx, level, R.ctypes.data, g.ctypes.data, a.ctypes.data, HOST))
+        return R, g, a
+
+    def time_steps(self, level=0):
+        n = self.sizes[level][0]
+        de, di = np.zeros(n), np.zeros(n)
+        self._check(_lib.cgks_time_steps(self.ctx, level, de.ctypes.data, di.ctypes.data))
+        return de, di
+
+    def smooth(self, level, n):
+        self._check(_lib.cgks_smooth(self.ctx, level, n))
+
+    def restrict(self, level):
+        self._check(_lib.cgks_restrict(self.ctx, level))
+
+    def prolong(self, level):
+        self._check(_lib.cgks_prolong(self.ctx, level))
+
+    def vcycle(self):
+        nrm = C.c_double()
+        self._check(_lib.cgks_vcycle(self.ctx, C.byref(nrm)))
+        return nrm.value
+
+    def run_cycles(self, n):
+        hist = np.zeros(n)
+        self._check(_lib.cgks_run_cycles(self.ctx, n, hist.ctypes.data_as(_D)))
+        return hist
+
+    def solve(self, tol=1e-10, max_cycles=1000):
+        hist = np.zeros(max_cycles)
+        ncyc = C.c_int()
+        rc = self._check(_lib.cgks_solve(self.ctx, C.c_double(tol), max_cycles, C.byref(ncyc),
+                                         hist.ctypes.data_as(_D), max_cycles))
+        return rc, hist[:ncyc.value]
+
+    def stats(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._check(_lib.cgks_stats(self.ctx, C.byref(a), C.byref(b)))
+        return a.value, b.value

@@ -1,0 +1,730 @@
+/*
+ * C ABI of libcgks: context, mesh upload, state transfer, the V-cycle
+ * sequence (captured once into a hipGraph and replayed), solve loop.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "cgks_internal.h"
+
+using namespace cgks;
+
+namespace {
+
+#define HIPCHK(expr)                                           \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #expr);   \
+    } while (0)
+
+template <class T>
+int dalloc(cgks_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    c->allocs.push_back((void*)*p);
+    return CGKS_OK;
+}
+
+template <class T>
+int h2d(cgks_ctx* c, T* d, const std::vector<T>& h) {
+    if (h.empty()) return CGKS_OK;
+    hipError_t e = hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy H2D");
+    return CGKS_OK;
+}
+
+template <class T>
+int d2h(cgks_ctx* c, std::vector<T>& h, const T* d, size_t count) {
+    h.resize(count);
+    hipError_t e = hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy D2H");
+    return CGKS_OK;
+}
+
+#define TRY(expr)                  \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != CGKS_OK) return rc_; \
+    } while (0)
+
+void free_device(cgks_ctx* c) {
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    c->graph = nullptr;
+    c->graph_tmpl = nullptr;
+    for (void* p : c->allocs) hipFree(p);
+    c->allocs.clear();
+}
+
+void make_kparams(cgks_ctx* c) {
+    const cgks_params& p = c->p;
+    KParams& k = c->kp;
+    k.dim = p.dim;
+    k.gamma = p.gamma;
+    k.K = 2.0 / (p.gamma - 1.0) - p.dim;
+    k.prandtl = p.prandtl;
+    k.mach = p.mach;
+    k.reynolds = p.reynolds;
+    k.mu_inf = p.reynolds > 0.0 ? p.mach / p.reynolds : 0.0;
+    k.Tinf = 1.0 / p.gamma;
+    k.S_suth = p.sutherland_S_ratio * k.Tinf;
+    k.Tw = p.wall_T_ratio * k.Tinf;
+    k.cfl_exp = p.cfl_exp;
+    k.cfl_imp = p.cfl_imp;
+    k.tau_c1 = p.tau_c1;
+    k.tau_c2 = p.tau_c2;
+    k.g_large = p.weno_gamma_large;
+    k.g_small = 1.0 - p.weno_gamma_large;
+    k.eps = p.weno_eps;
+    k.omega = p.lusgs_omega;
+    k.df_relax = p.df_relax;
+    k.df_prolong = p.df_prolong;
+    const double a = p.aoa_deg * M_PI / 180.0;
+    k.u_inf[0] = p.mach * std::cos(a);
+    k.u_inf[1] = p.mach * std::sin(a);
+    k.u_inf[2] = 0.0;
+}
+
+int check_level(cgks_ctx* c, int level) {
+    if (!c) return CGKS_EINVAL;
+    if (!c->have_mesh) return fail(c, CGKS_EINVAL, "no mesh: call cgks_mesh_setup first");
+    if (level < 0 || level >= (int)c->hl.size()) return fail(c, CGKS_EINVAL, "level out of range");
+    return CGKS_OK;
+}
+
+/* AoS original-order host array <-> SoA internal-order device array. */
+void aos_to_soa(const double* in, std::vector<double>& out, int n, int m, const std::vector<int>& perm) {
+    out.assign((size_t)n * m, 0.0);
+    for (int I = 0; I < n; ++I)
+        for (int q = 0; q < m; ++q) out[(size_t)q * n + I] = in[(size_t)perm[I] * m + q];
+}
+
+void soa_to_aos(const std::vector<double>& in, double* out, int n, int m, const std::vector<int>& perm) {
+    for (int I = 0; I < n; ++I)
+        for (int q = 0; q < m; ++q) out[(size_t)perm[I] * m + q] = in[(size_t)q * n + I];
+}
+
+int fetch_aos(cgks_ctx* c, const double* dsrc, double* out, int n, int m, const std::vector<int>& perm, int mem) {
+    std::vector<double> h;
+    TRY(d2h(c, h, dsrc, (size_t)n * m));
+    if (mem == CGKS_DEVICE) {
+        std::vector<double> a((size_t)n * m);
+        soa_to_aos(h, a.data(), n, m, perm);
+        hipError_t e = hipMemcpy(out, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy to caller");
+    } else {
+        soa_to_aos(h, out, n, m, perm);
+    }
+    return CGKS_OK;
+}
+
+int store_aos(cgks_ctx* c, double* ddst, const double* in, int n, int m, const std::vector<int>& perm, int mem) {
+    std::vector<double> a;
+    const double* src = in;
+    if (mem == CGKS_DEVICE) {
+        a.resize((size_t)n * m);
+        hipError_t e = hipMemcpy(a.data(), in, a.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy from caller");
+        src = a.data();
+    }
+    std::vector<double> s;
+    aos_to_soa(src, s, n, m, perm);
+    HIPCHK(hipMemcpyAsync(ddst, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+void enqueue_restrict(cgks_ctx* c, int l) {
+    if (l == 0)
+        launch_fine_residual(c, FINE_RESTRICT);
+    else
+        launch_coarse_rhs(c, l, COARSE_RHS);
+    launch_restrict(c, l);
+    launch_coarse_rhs(c, l + 1, COARSE_FORCING);
+}
+
+void enqueue_lusgs_iter(cgks_ctx* c, int l) {
+    launch_coarse_rhs(c, l, COARSE_RHS);
+    launch_lusgs(c, l);
+    launch_coarse_update(c, l);
+}
+
+/* One V-cycle: fine pre-smoothing, restriction, coarse LU-SGS, prolongation. */
+void enqueue_vcycle(cgks_ctx* c) {
+    const int nl = (int)c->hl.size();
+    launch_save_state(c);
+    for (int s = 0; s < c->p.n_pre_fine; ++s) launch_fine_residual(c, s == 0 ? FINE_STEP_NORM : FINE_STEP);
+    for (int l = 0; l + 1 < nl; ++l) {
+        enqueue_restrict(c, l);
+        for (int s = 0; s < c->p.n_sweeps; ++s) enqueue_lusgs_iter(c, l + 1);
+    }
+    for (int l = nl - 2; l >= 0; --l) launch_prolong(c, l);
+}
+
+int ensure_history(cgks_ctx* c, int need) {
+    if (need <= c->ws.history_cap) return CGKS_OK;
+    /* the captured graph refers to the old buffer */
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    c->graph = nullptr;
+    c->graph_tmpl = nullptr;
+    int cap = std::max(need, 2 * c->ws.history_cap);
+    double* h;
+    TRY(dalloc(c, &h, cap));
+    c->ws.history = h;
+    c->ws.history_cap = cap;
+    return CGKS_OK;
+}
+
+int build_graph(cgks_ctx* c) {
+    if (c->graph) return CGKS_OK;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_vcycle(c);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    c->graph_tmpl = g;
+    HIPCHK(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+    return CGKS_OK;
+}
+
+int restore_saved(cgks_ctx* c) {
+    FineDev& f = c->fine;
+    const size_t n = f.n, nv = c->nv, d = c->dim;
+    HIPCHK(hipMemcpyAsync(f.W, f.Wsave, n * nv * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(f.grad, f.gsave, n * nv * d * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(f.alpha, f.asave, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+int set_counters(cgks_ctx* c) {
+    static const int zero[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c->ws.counter, &zero[0], sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ws.status, &zero[1], sizeof(int), hipMemcpyHostToDevice, c->stream));
+    return CGKS_OK;
+}
+
+}  // namespace
+
+namespace cgks {
+
+int upload(cgks_ctx* c) {
+    free_device(c);
+    const int dim = c->dim, nv = c->nv;
+    HLevel& H = c->hl[0];
+    FineDev& f = c->fine;
+    std::memset(&f, 0, sizeof(f));
+    f.n = H.n;
+    f.nf = (int)H.faces.size();
+    f.ngp = (dim == 2) ? 2 : 3;
+    f.nslot = dim + 1;
+    f.nb = (dim == 2) ? 5 : 9;
+    const int n = f.n, nf = f.nf, ng = f.ngp, ns = f.nslot, nq = f.nb;
+    const int ncol = ns * (1 + dim);
+    std::vector<double> Cs((size_t)dim * n), fn((size_t)dim * nf), fS(nf), fgp((size_t)ng * dim * nf);
+    std::vector<int> sface((size_t)ns * n), snbr((size_t)ns * n), fL(nf), fR(nf), ftag(nf);
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < dim; ++d) Cs[(size_t)d * n + i] = H.C[(size_t)i * dim + d];
+    for (int k = 0; k < nf; ++k) {
+        const HFace& F = H.faces[k];
+        fL[k] = F.L;
+        fR[k] = F.R;
+        ftag[k] = F.tag;
+        fS[k] = F.S;
+        for (int d = 0; d < dim; ++d) {
+            fn[(size_t)d * nf + k] = F.n[d];
+            for (int g = 0; g < ng; ++g) fgp[((size_t)g * dim + d) * nf + k] = F.gp[g][d];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < ns; ++s) {
+            const int k = H.cf[i][s];
+            const HFace& F = H.faces[k];
+            const int side = (F.L == i) ? 0 : 1;
+            sface[(size_t)s * n + i] = k * 2 + side;
+            snbr[(size_t)s * n + i] = (F.R < 0) ? -1 : (side ? F.L : F.R);
+        }
+    TRY(dalloc(c, &f.V, n)); TRY(h2d(c, f.V, H.V));
+    TRY(dalloc(c, &f.C, (size_t)dim * n)); TRY(h2d(c, f.C, Cs));
+    TRY(dalloc(c, &f.h, n)); TRY(h2d(c, f.h, H.h));
+    TRY(dalloc(c, &f.mean0, (size_t)nq * n)); TRY(h2d(c, f.mean0, H.mean0));
+    TRY(dalloc(c, &f.op, (size_t)nq * ncol * n)); TRY(h2d(c, f.op, H.op));
+    TRY(dalloc(c, &f.slot_face, (size_t)ns * n)); TRY(h2d(c, f.slot_face, sface));
+    TRY(dalloc(c, &f.slot_nbr, (size_t)ns * n)); TRY(h2d(c, f.slot_nbr, snbr));
+    TRY(dalloc(c, &f.fL, nf)); TRY(h2d(c, f.fL, fL));
+    TRY(dalloc(c, &f.fR, nf)); TRY(h2d(c, f.fR, fR));
+    TRY(dalloc(c, &f.ftag, nf)); TRY(h2d(c, f.ftag, ftag));
+    TRY(dalloc(c, &f.fn, (size_t)dim * nf)); TRY(h2d(c, f.fn, fn));
+    TRY(dalloc(c, &f.fS, nf)); TRY(h2d(c, f.fS, fS));
+    TRY(dalloc(c, &f.fgp, (size_t)ng * dim * nf)); TRY(h2d(c, f.fgp, fgp));
+    TRY(dalloc(c, &f.W, (size_t)nv * n));
+    TRY(dalloc(c, &f.grad, (size_t)nv * dim * n));
+    TRY(dalloc(c, &f.alpha, n));
+    TRY(dalloc(c, &f.Wsave, (size_t)nv * n));
+    TRY(dalloc(c, &f.gsave, (size_t)nv * dim * n));
+    TRY(dalloc(c, &f.asave, n));
+    TRY(dalloc(c, &f.gpst, (size_t)2 * ng * nv * (1 + dim) * nf));
+    TRY(dalloc(c, &f.fF, (size_t)nv * ng * nf));
+    TRY(dalloc(c, &f.fG, (size_t)nv * ng * nf));
+    TRY(dalloc(c, &f.fa, (size_t)ng * nf));
+    TRY(dalloc(c, &f.R, (size_t)nv * n));
+    TRY(dalloc(c, &f.gnew, (size_t)nv * dim * n));
+    TRY(dalloc(c, &f.anew, n));
+    TRY(dalloc(c, &f.dt, n));
+    TRY(dalloc(c, &f.dti, n));
+    TRY(dalloc(c, &f.res, (size_t)nv * n));
+    TRY(dalloc(c, &f.guard, 1));
+    HIPCHK(hipMemset(f.guard, 0, sizeof(unsigned long long)));
+
+    c->coarse.assign(c->hl.size() - 1, CoarseDev());
+    for (size_t l = 1; l < c->hl.size(); ++l) {
+        HLevel& G = c->hl[l];
+        HLevel& Fh = c->hl[l - 1];
+        CoarseDev& D = c->coarse[l - 1];
+        D.n = G.n;
+        D.nslot = G.nslot;
+        D.ncolor = G.ncolor;
+        D.color_off = G.color_off;
+        const int m = G.n, S = G.nslot;
+        std::vector<int> nb((size_t)S * m, -1), tg((size_t)S * m, 0);
+        std::vector<double> sS((size_t)S * m, 0.0), sn((size_t)dim * S * m, 0.0), sd((size_t)S * m, 1.0), V(m);
+        for (int I = 0; I < m; ++I) {
+            const int o = G.perm[I];
+            V[I] = G.V[o];
+            for (int s = 0; s < (int)G.cf[o].size(); ++s) {
+                const HFace& F = G.faces[G.cf[o][s]];
+                const double sg = (F.L == o) ? 1.0 : -1.0;
+                sS[(size_t)s * m + I] = F.S;
+                for (int d = 0; d < dim; ++d) sn[((size_t)d * S + s) * m + I] = sg * F.n[d];
+                double dist = 0.0;
+                if (F.R >= 0) {
+                    const int j = (F.L == o) ? F.R : F.L;
+                    nb[(size_t)s * m + I] = G.iperm[j];
+                    for (int d = 0; d < dim; ++d) {
+                        const double dx = G.C[(size_t)j * dim + d] - G.C[(size_t)o * dim + d];
+                        dist += dx * dx;
+                    }
+                    sd[(size_t)s * m + I] = std::sqrt(dist);
+                } else {
+                    tg[(size_t)s * m + I] = F.tag;
+                    for (int d = 0; d < dim; ++d) {
+                        const double dx = F.xc[d] - G.C[(size_t)o * dim + d];
+                        dist += dx * dx;
+                    }
+                    sd[(size_t)s * m + I] = 2.0 * std::sqrt(dist);
+                }
+            }
+        }
+        /* transfers: parent of each finer internal cell, children CSR of finer internal cells */
+        const int nfine = Fh.n;
+        std::vector<int> par(nfine), coff(m + 1, 0), ch;
+        for (int j = 0; j < nfine; ++j) par[j] = G.iperm[Fh.parent[Fh.perm[j]]];
+        ch.reserve(nfine);
+        for (int I = 0; I < m; ++I) {
+            const int o = G.perm[I];
+            std::vector<int> kids;
+            for (int i : G.children[o]) kids.push_back(Fh.iperm[i]);
+            std::sort(kids.begin(), kids.end());
+            for (int k : kids) ch.push_back(k);
+            coff[I + 1] = (int)ch.size();
+        }
+        TRY(dalloc(c, &D.V, m)); TRY(h2d(c, D.V, V));
+        D.C = nullptr;
+        TRY(dalloc(c, &D.snbr, (size_t)S * m)); TRY(h2d(c, D.snbr, nb));
+        TRY(dalloc(c, &D.stag, (size_t)S * m)); TRY(h2d(c, D.stag, tg));
+        TRY(dalloc(c, &D.sS, (size_t)S * m)); TRY(h2d(c, D.sS, sS));
+        TRY(dalloc(c, &D.sn, (size_t)dim * S * m)); TRY(h2d(c, D.sn, sn));
+        TRY(dalloc(c, &D.sd, (size_t)S * m)); TRY(h2d(c, D.sd, sd));
+        for (double** p : {&D.W, &D.W0, &D.F, &D.Rstar, &D.dW, &D.rhs}) TRY(dalloc(c, p, (size_t)nv * m));
+        for (double** p : {&D.alpha, &D.D, &D.dte, &D.dti}) TRY(dalloc(c, p, m));
+        TRY(dalloc(c, &D.r, (size_t)S * m));
+        TRY(dalloc(c, &D.parent, nfine)); TRY(h2d(c, D.parent, par));
+        TRY(dalloc(c, &D.child_off, m + 1)); TRY(h2d(c, D.child_off, coff));
+        TRY(dalloc(c, &D.child, nfine)); TRY(h2d(c, D.child, ch));
+        HIPCHK(hipMemset(D.F, 0, (size_t)nv * m * sizeof(double)));
+        HIPCHK(hipMemset(D.dW, 0, (size_t)nv * m * sizeof(double)));
+    }
+    Workspace& w = c->ws;
+    w = Workspace();
+    w.npartial = (n + 255) / 256;
+    TRY(dalloc(c, &w.partial, w.npartial));
+    TRY(dalloc(c, &w.counter, 1));
+    TRY(dalloc(c, &w.status, 1));
+    TRY(dalloc(c, &w.skips, 1));
+    HIPCHK(hipMemset(w.skips, 0, sizeof(unsigned long long)));
+    HIPCHK(hipMemset(w.counter, 0, sizeof(int)));
+    HIPCHK(hipMemset(w.status, 0, sizeof(int)));
+    TRY(ensure_history(c, 1024));
+    HIPCHK(hipDeviceSynchronize());
+    return CGKS_OK;
+}
+
+}  // namespace cgks
+
+extern "C" {
+
+void cgks_default_params(cgks_params* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->dim = 2;
+    p->gamma = 1.4;
+    p->prandtl = 0.72;
+    p->mach = 0.5;
+    p->aoa_deg = 0.0;
+    p->reynolds = 0.0;
+    p->wall_T_ratio = 1.0;
+    p->sutherland_S_ratio = 0.5;
+    p->cfl_exp = 0.5;
+    p->cfl_imp = 10.0;
+    p->n_levels = 3;
+    p->n_pre_fine = 1;
+    p->n_post = 0;
+    p->n_sweeps = 6;
+    p->df_relax = 1;
+    p->df_prolong = 1;
+    p->precision = CGKS_FP64;
+    p->tau_c1 = 0.01;
+    p->tau_c2 = 1.0;
+    p->weno_gamma_large = 0.95;
+    p->weno_eps = 1e-14;
+    p->lusgs_omega = 1.0;
+    p->skew_limit = 0.2;
+}
+
+const char* cgks_strerror(int code) {
+    switch (code) {
+        case CGKS_OK: return "ok";
+        case CGKS_NOTCONV: return "not converged within max_cycles";
+        case CGKS_EINVAL: return "invalid argument";
+        case CGKS_EMESH: return "invalid mesh";
+        case CGKS_EDEVICE: return "HIP device error";
+        case CGKS_ENONPHYS: return "non-physical state";
+        default: return "unknown error";
+    }
+}
+
+const char* cgks_last_error(const cgks_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int cgks_create(const cgks_params* p, cgks_ctx** out) {
+    if (!p || !out) return CGKS_EINVAL;
+    *out = nullptr;
+    if (p->dim != 2 && p->dim != 3) return CGKS_EINVAL;
+    if (p->n_post != 0 || p->n_pre_fine < 1 || p->n_sweeps < 0 || !(p->mach > 0.0) || !(p->gamma > 1.0))
+        return CGKS_EINVAL;
+    if (p->precision != CGKS_FP64) return CGKS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
+    cgks_ctx* c = new cgks_ctx();
+    c->p = *p;
+    c->dim = p->dim;
+    c->nv = p->dim + 2;
+    hipGetDevice(&c->device);
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return CGKS_EDEVICE;
+    }
+    c->stream = c->own_stream;
+    make_kparams(c);
+    *out = c;
+    return CGKS_OK;
+}
+
+void cgks_destroy(cgks_ctx* c) {
+    if (!c) return;
+    hipDeviceSynchronize();
+    free_device(c);
+    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+int cgks_set_stream(cgks_ctx* c, void* stream) {
+    if (!c) return CGKS_EINVAL;
+    c->stream = stream ? (hipStream_t)stream : c->own_stream;
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    c->graph = nullptr;
+    c->graph_tmpl = nullptr;
+    return CGKS_OK;
+}
+
+int cgks_mesh_setup(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* const* parent) {
+    if (!c || !m) return CGKS_EINVAL;
+    c->have_mesh = false;
+    int rc = setup_host(c, m, n_levels, parent);
+    if (rc) return rc;
+    rc = upload(c);
+    if (rc) return rc;
+    c->have_mesh = true;
+    return CGKS_OK;
+}
+
+int cgks_level_size(cgks_ctx* c, int level, int* n_cells, int* n_faces) {
+    TRY(check_level(c, level));
+    if (n_cells) *n_cells = c->hl[level].n;
+    if (n_faces) *n_faces = (int)c->hl[level].faces.size();
+    return CGKS_OK;
+}
+
+int cgks_coloring(cgks_ctx* c, int level, int32_t* color_out, int32_t* n_colors) {
+    TRY(check_level(c, level));
+    const HLevel& H = c->hl[level];
+    if (color_out)
+        for (int i = 0; i < H.n; ++i) color_out[i] = H.color[i];
+    if (n_colors) *n_colors = H.ncolor;
+    return CGKS_OK;
+}
+
+int cgks_agglomerate(cgks_ctx* c, int level, int32_t* agg_out, int32_t* n_coarse) {
+    TRY(check_level(c, level));
+    std::vector<int> agg;
+    int nc = agglomerate_level(c, level, agg);
+    if (agg_out)
+        for (size_t i = 0; i < agg.size(); ++i) agg_out[i] = agg[i];
+    if (n_coarse) *n_coarse = nc;
+    return CGKS_OK;
+}
+
+int cgks_cell_geometry(cgks_ctx* c, int level, double* V, double* C) {
+    TRY(check_level(c, level));
+    const HLevel& H = c->hl[level];
+    if (V) std::copy(H.V.begin(), H.V.end(), V);
+    if (C) std::copy(H.C.begin(), H.C.end(), C);
+    return CGKS_OK;
+}
+
+int cgks_init_freestream(cgks_ctx* c) {
+    TRY(check_level(c, 0));
+    const int nv = c->nv, dim = c->dim;
+    double Winf[5];
+    Winf[0] = 1.0;
+    double ke = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        Winf[1 + d] = c->kp.u_inf[d];
+        ke += c->kp.u_inf[d] * c->kp.u_inf[d];
+    }
+    Winf[dim + 1] = (1.0 / c->p.gamma) / (c->p.gamma - 1.0) + 0.5 * ke;
+    for (size_t l = 0; l < c->hl.size(); ++l) {
+        const int n = c->hl[l].n;
+        std::vector<double> W((size_t)nv * n), a(n, 1.0);
+        for (int q = 0; q < nv; ++q)
+            for (int i = 0; i < n; ++i) W[(size_t)q * n + i] = Winf[q];
+        if (l == 0) {
+            TRY(h2d(c, c->fine.W, W));
+            TRY(h2d(c, c->fine.alpha, a));
+            HIPCHK(hipMemset(c->fine.grad, 0, (size_t)nv * dim * n * sizeof(double)));
+        } else {
+            CoarseDev& D = c->coarse[l - 1];
+            TRY(h2d(c, D.W, W));
+            TRY(h2d(c, D.W0, W));
+            TRY(h2d(c, D.alpha, a));
+            HIPCHK(hipMemset(D.F, 0, (size_t)nv * n * sizeof(double)));
+        }
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return CGKS_OK;
+}
+
+int cgks_set_state(cgks_ctx* c, const double* W, const double* gradW, const double* alpha, int mem) {
+    TRY(check_level(c, 0));
+    if (!W) return fail(c, CGKS_EINVAL, "W is NULL");
+    const HLevel& H = c->hl[0];
+    const int n = H.n, nv = c->nv, dim = c->dim;
+    TRY(store_aos(c, c->fine.W, W, n, nv, H.perm, mem));
+    if (gradW) {
+        TRY(store_aos(c, c->fine.grad, gradW, n, nv * dim, H.perm, mem));
+    } else {
+        HIPCHK(hipMemset(c->fine.grad, 0, (size_t)nv * dim * n * sizeof(double)));
+    }
+    if (alpha) {
+        TRY(store_aos(c, c->fine.alpha, alpha, n, 1, H.perm, mem));
+    } else {
+        std::vector<double> a(n, 1.0);
+        TRY(h2d(c, c->fine.alpha, a));
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return CGKS_OK;
+}
+
+int cgks_get_state(cgks_ctx* c, double* W, double* gradW, double* alpha, int mem) {
+    TRY(check_level(c, 0));
+    const HLevel& H = c->hl[0];
+    const int n = H.n, nv = c->nv, dim = c->dim;
+    if (W) TRY(fetch_aos(c, c->fine.W, W, n, nv, H.perm, mem));
+    if (gradW) TRY(fetch_aos(c, c->fine.grad, gradW, n, nv * dim, H.perm, mem));
+    if (alpha) TRY(fetch_aos(c, c->fine.alpha, alpha, n, 1, H.perm, mem));
+    return CGKS_OK;
+}
+
+int cgks_set_level_state(cgks_ctx* c, int level, const double* W, const double* W0, const double* F,
+                         const double* alpha) {
+    TRY(check_level(c, level));
+    if (level == 0) return cgks_set_state(c, W, nullptr, alpha, CGKS_HOST);
+    const HLevel& H = c->hl[level];
+    CoarseDev& D = c->coarse[level - 1];
+    const int n = H.n, nv = c->nv;
+    if (W) TRY(store_aos(c, D.W, W, n, nv, H.perm, CGKS_HOST));
+    if (W0) TRY(store_aos(c, D.W0, W0, n, nv, H.perm, CGKS_HOST));
+    if (F) TRY(store_aos(c, D.F, F, n, nv, H.perm, CGKS_HOST));
+    if (alpha) TRY(store_aos(c, D.alpha, alpha, n, 1, H.perm, CGKS_HOST));
+    return CGKS_OK;
+}
+
+int cgks_get_level_state(cgks_ctx* c, int level, double* W, double* W0, double* F, double* alpha) {
+    TRY(check_level(c, level));
+    if (level == 0) return cgks_get_state(c, W, nullptr, alpha, CGKS_HOST);
+    const HLevel& H = c->hl[level];
+    CoarseDev& D = c->coarse[level - 1];
+    const int n = H.n, nv = c->nv;
+    if (W) TRY(fetch_aos(c, D.W, W, n, nv, H.perm, CGKS_HOST));
+    if (W0) TRY(fetch_aos(c, D.W0, W0, n, nv, H.perm, CGKS_HOST));
+    if (F) TRY(fetch_aos(c, D.F, F, n, nv, H.perm, CGKS_HOST));
+    if (alpha) TRY(fetch_aos(c, D.alpha, alpha, n, 1, H.perm, CGKS_HOST));
+    return CGKS_OK;
+}
+
+int cgks_residual(cgks_ctx* c, int level, double* R, double* gradW_new, double* alpha_out, int mem) {
+    TRY(check_level(c, level));
+    const HLevel& H = c->hl[level];
+    const int n = H.n, nv = c->nv, dim = c->dim;
+    if (level == 0) {
+        launch_fine_residual(c, FINE_EVAL);
+        HIPCHK(hipGetLastError());
+        if (R) TRY(fetch_aos(c, c->fine.R, R, n, nv, H.perm, mem));
+        if (gradW_new) TRY(fetch_aos(c, c->fine.gnew, gradW_new, n, nv * dim, H.perm, mem));
+        if (alpha_out) TRY(fetch_aos(c, c->fine.anew, alpha_out, n, 1, H.perm, mem));
+        return CGKS_OK;
+    }
+    CoarseDev& D = c->coarse[level - 1];
+    launch_coarse_rhs(c, level, COARSE_RHS);
+    HIPCHK(hipGetLastError());
+    if (R) {
+        std::vector<double> h;
+        TRY(d2h(c, h, D.rhs, (size_t)nv * n));
+        for (double& v : h) v = -v;
+        if (mem == CGKS_DEVICE) {
+            std::vector<double> a((size_t)n * nv);
+            soa_to_aos(h, a.data(), n, nv, H.perm);
+            HIPCHK(hipMemcpy(R, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            soa_to_aos(h, R, n, nv, H.perm);
+        }
+    }
+    if (alpha_out) TRY(fetch_aos(c, D.alpha, alpha_out, n, 1, H.perm, mem));
+    return CGKS_OK;
+}
+
+int cgks_time_steps(cgks_ctx* c, int level, double* dt_exp, double* dt_imp) {
+    TRY(check_level(c, level));
+    const HLevel& H = c->hl[level];
+    const int n = H.n;
+    const double *de, *di;
+    if (level == 0) {
+        launch_fine_recon(c);
+        de = c->fine.dt;
+        di = c->fine.dti;
+    } else {
+        launch_coarse_rhs(c, level, COARSE_RHS);
+        de = c->coarse[level - 1].dte;
+        di = c->coarse[level - 1].dti;
+    }
+    HIPCHK(hipGetLastError());
+    if (dt_exp) TRY(fetch_aos(c, de, dt_exp, n, 1, H.perm, CGKS_HOST));
+    if (dt_imp) TRY(fetch_aos(c, di, dt_imp, n, 1, H.perm, CGKS_HOST));
+    return CGKS_OK;
+}
+
+int cgks_smooth(cgks_ctx* c, int level, int n) {
+    TRY(check_level(c, level));
+    for (int s = 0; s < n; ++s) {
+        if (level == 0)
+            launch_fine_residual(c, FINE_STEP);
+        else
+            enqueue_lusgs_iter(c, level);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+int cgks_restrict(cgks_ctx* c, int level) {
+    TRY(check_level(c, level));
+    if (level + 1 >= (int)c->hl.size()) return fail(c, CGKS_EINVAL, "no coarser level");
+    enqueue_restrict(c, level);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+int cgks_prolong(cgks_ctx* c, int level) {
+    TRY(check_level(c, level));
+    if (level + 1 >= (int)c->hl.size()) return fail(c, CGKS_EINVAL, "no coarser level");
+    launch_prolong(c, level);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+int cgks_run_cycles(cgks_ctx* c, int ncyc, double* history) {
+    TRY(check_level(c, 0));
+    if (ncyc <= 0) return CGKS_OK;
+    TRY(ensure_history(c, ncyc));
+    TRY(build_graph(c));
+    TRY(set_counters(c));
+    for (int k = 0; k < ncyc; ++k) HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    int status = 0;
+    HIPCHK(hipMemcpyAsync(&status, c->ws.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (history) HIPCHK(hipMemcpyAsync(history, c->ws.history, ncyc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->cycles_done += ncyc;
+    if (status) {
+        TRY(restore_saved(c));
+        return fail(c, CGKS_ENONPHYS, "non-physical state (NaN, rho <= 0 or p <= 0); state rolled back");
+    }
+    return CGKS_OK;
+}
+
+int cgks_vcycle(cgks_ctx* c, double* norm_out) {
+    double h = 0.0;
+    int rc = cgks_run_cycles(c, 1, &h);
+    if (norm_out) *norm_out = h;
+    return rc;
+}
+
+int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double* history, int history_cap) {
+    TRY(check_level(c, 0));
+    int done = 0;
+    int chunk = 8;
+    std::vector<double> h;
+    while (done < max_cycles) {
+        const int k = std::min(chunk, max_cycles - done);
+        h.assign(k, 0.0);
+        int rc = cgks_run_cycles(c, k, h.data());
+        for (int j = 0; j < k; ++j) {
+            if (history && done + j < history_cap) history[done + j] = h[j];
+            if (h[j] <= tol) {
+                if (cycles_out) *cycles_out = done + j + 1;
+                return rc;
+            }
+        }
+        done += k;
+        if (cycles_out) *cycles_out = done;
+        if (rc) return rc;
+        chunk = std::min(64, chunk * 2);
+    }
+    return CGKS_NOTCONV;
+}
+
+int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
+    TRY(check_level(c, 0));
+    unsigned long long g = 0, s = 0;
+    HIPCHK(hipMemcpy(&g, c->fine.guard, sizeof(g), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&s, c->ws.skips, sizeof(s), hipMemcpyDeviceToHost));
+    if (guard_hits) *guard_hits = (int64_t)g;
+    if (prolong_skips) *prolong_skips = (int64_t)s;
+    return CGKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+/*
+ * Internal declarations of libcgks (host set-up, device buffers, launchers).
+ */
+#ifndef CGKS_INTERNAL_H
+#define CGKS_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cgks.h"
+
+namespace cgks {
+
+constexpr int MAXV = 5;      /* conservative variables, 3-D */
+constexpr int MAXD = 3;
+
+/* ---------------------------------------------------------------- host --- */
+
+struct HFace {
+    int L, R, tag;       /* R < 0: boundary face with tag */
+    double n[3];         /* unit normal L -> R */
+    double S;            /* area (2-D: length) */
+    double xc[3];        /* centre */
+    int ngp;
+    double gp[3][3];     /* Gauss points */
+};
+
+struct HLevel {
+    int n = 0;
+    std::vector<double> V, C;             /* original order */
+    std::vector<HFace> faces;             /* fine: canonical faces; coarse: agglomerate pairs */
+    std::vector<std::vector<int>> cf;     /* per cell: face ids in local order */
+    std::vector<int> parent;              /* original index on the next coarser level */
+    std::vector<std::vector<int>> children;
+    std::vector<int> color;               /* 1..ncolor, original order */
+    int ncolor = 0;
+    std::vector<int> perm, iperm;         /* internal -> original, original -> internal */
+    std::vector<int> color_off;           /* internal offsets of each colour, size ncolor+1 */
+    int nslot = 0;                        /* max faces per cell */
+    /* fine level only */
+    std::vector<int> nodes;
+    std::vector<double> h, mean0, op;     /* basis scale, basis means, LS operator (slot layout) */
+    std::vector<int> nbasis;              /* per cell: quadratic, linear or constant basis */
+};
+
+/* --------------------------------------------------------------- device --- */
+
+/* Fine level, structure of arrays with the cell (or face) index fastest. */
+struct FineDev {
+    int n, nf, ngp, nslot, nb;
+    double *V, *C, *h, *mean0, *op;   /* op: [nb][nslot*(1+dim)][n] */
+    int *slot_face;                   /* [nslot][n]: face id * 2 + side (side 1 = cell is R) */
+    int *slot_nbr;                    /* [nslot][n]: neighbour or -1 */
+    int *fL, *fR, *ftag;
+    double *fn, *fS, *fgp;            /* fn [dim][nf], fgp [ngp][dim][nf] */
+    double *W, *grad, *alpha;         /* state */
+    double *Wsave, *gsave, *asave;    /* start-of-cycle copy for roll-back */
+    double *gpst;                     /* [2][ngp][nv + nv*dim][nf] Gauss-point states */
+    double *fF, *fG, *fa;             /* [nv][ngp*nf], [nv][ngp*nf], [ngp*nf] */
+    double *R, *gnew, *anew, *dt, *dti;
+    double *res;                      /* -R of the restriction evaluation */
+    unsigned long long* guard;        /* positivity-guard hit counter */
+};
+
+struct CoarseDev {
+    int n, nslot, ncolor;
+    std::vector<int> color_off;       /* host copy */
+    double *V, *C;
+    int *snbr, *stag;                 /* [nslot][n] (internal neighbour, -1 boundary / empty) */
+    double *sS, *sn, *sd;             /* [nslot][n], [dim][nslot][n], [nslot][n] viscous distance */
+    double *W, *W0, *F, *Rstar, *alpha, *dW, *rhs, *D, *r, *dte, *dti;
+    int *parent;                      /* of the finer level's internal cells: this level's internal index */
+    int *child_off, *child;           /* CSR of finer internal indices */
+};
+
+struct Workspace {
+    double* partial = nullptr;        /* per-block norm partial sums */
+    int npartial = 0;
+    double* history = nullptr;        /* device norm history */
+    int history_cap = 0;
+    int* counter = nullptr;           /* device cycle counter */
+    unsigned long long* skips = nullptr;
+    int* status = nullptr;            /* non-physical flag */
+};
+
+/* Scalar parameters as seen by the kernels. */
+struct KParams {
+    int dim;
+    double gamma, K, prandtl, mach, reynolds, mu_inf, Tinf, S_suth, Tw;
+    double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega;
+    int df_relax, df_prolong;
+    double u_inf[3];
+};
+
+}  // namespace cgks
+
+struct cgks_ctx {
+    cgks_params p;
+    cgks::KParams kp;
+    int dim = 2, nv = 4;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;     /* used when the caller sets no stream */
+    std::string err;
+    bool have_mesh = false;
+    std::vector<double> coords;
+    std::vector<cgks::HLevel> hl;
+    cgks::FineDev fine{};
+    std::vector<cgks::CoarseDev> coarse;   /* index l-1 for level l */
+    cgks::Workspace ws;
+    std::vector<void*> allocs;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_tmpl = nullptr;
+    int cycles_done = 0;
+};
+
+namespace cgks {
+int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* const* parent);
+int agglomerate_level(const cgks_ctx* c, int level, std::vector<int>& agg);
+int upload(cgks_ctx* c);
+int fail(cgks_ctx* c, int code, const std::string& msg);
+int hip_fail(cgks_ctx* c, hipError_t e, const char* what);
+
+/* kernel launchers (kernels_fine.hip / kernels_coarse.hip) */
+void launch_fine_residual(cgks_ctx* c, int mode);
+void launch_fine_recon(cgks_ctx* c);
+void launch_coarse_rhs(cgks_ctx* c, int level, int mode);
+void launch_lusgs(cgks_ctx* c, int level);
+void launch_restrict(cgks_ctx* c, int level);
+void launch_prolong(cgks_ctx* c, int level);
+void launch_norm_finalize(cgks_ctx* c);
+void launch_save_state(cgks_ctx* c);
+void launch_coarse_update(cgks_ctx* c, int level);
+
+/* modes of launch_fine_residual */
+enum { FINE_EVAL = 0, FINE_STEP = 1, FINE_STEP_NORM = 2, FINE_RESTRICT = 3 };
+/* modes of launch_coarse_rhs */
+enum { COARSE_RHS = 0, COARSE_FORCING = 1 };
+}  // namespace cgks
+
+#endif
