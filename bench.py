@@ -1,0 +1,143 @@
+"""Benchmark of the multigrid CGKS V-cycle on one MI355X.
+
+Workload (default): the viscous Mach 8 cylinder, Re = 1e4 per diameter,
+Pr = 0.72, gamma = 1.4, isothermal wall T_w/T_inf = 1; 128 x 32 coarsest
+annulus quads (radial stretching 1.2, seeded +-0.1h node jitter) split into
+triangles and refined twice -> 131,072 fine triangles on 3 nested levels.
+
+A "step" is one full 3-level V-cycle (fine residual, explicit fine step,
+second fine residual, restriction, 6 multi-colour LU-SGS iterations on each
+coarse level, DF-limited prolongation).  Inputs are resident in HBM before
+the timed region; K V-cycles are replayed from a captured hipGraph between
+two events on the solver's stream.
+
+Printed: one JSON line with the metric (Mcell * V-cycles / s), the roofline
+of the dominant kernel (the Gauss-point BGK flux, FP64-ALU bound, timed with
+HIP events on the solver's stream) and the CPU oracle timed on one V-cycle of
+the same workload as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell·V-cycles/s and time-to-1e-10 residual, plain FP64 vs chosen form"
+
+# Algorithmic FP64 operations of one Gauss-point evaluation of the 2-D BGK
+# flux kernel (k_flux): +,-,*,/, sqrt and each transcendental counted as one
+# operation, counted by running the kernel's own source on a counting number
+# type ("Roofline").  Navier-Stokes branch (heat-flux fix) on.
+FLUX_FLOPS_PER_GP_NS = 4983
+FLUX_FLOPS_PER_GP_EULER = 4948
+MI355X_FP64_VECTOR_TFLOPS = 78.6
+
+
+def workload(name):
+    import synthmesh as sm
+    if name == "cylinder_ns_mach8_131k":
+        return sm.cylinder_ns_large(), dict(mach=8.0, reynolds=1e4, prandtl=0.72, wall_T_ratio=1.0)
+    if name == "cylinder_euler_mach038_8k":
+        return sm.cylinder_euler_small(), dict(mach=0.38)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def initial_state(solver, mesh, params):
+    """Free stream, with the velocity ramped to zero at a no-slip wall."""
+    import numpy as np
+    solver.init_freestream()
+    if params.get("reynolds", 0.0) > 0.0:
+        W, _, _ = solver.get_state()
+        V, C = solver.cell_geometry(0)
+        r = np.tanh((np.hypot(C[:, 0], C[:, 1]) - 0.5) / 0.3)
+        W[:, 1] *= r
+        W[:, 2] *= r
+        W[:, 3] = (1.0 / 1.4) / 0.4 + 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0]
+        solver.set_state(W)
+        return W
+    W, _, _ = solver.get_state()
+    return W
+
+
+def cpu_baseline(mesh, params, W0, n_fine):
+    """The CPU oracle (single thread, as it stands) on one V-cycle of the same workload."""
+    from oracle import orc
+    o = orc.Oracle(mesh, n_levels=3, **params)
+    o.set_state(W0)
+    t = time.perf_counter()
+    o.vcycle()
+    dt = time.perf_counter() - t
+    return {"value": n_fine / dt / 1e6, "unit": "Mcell·V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 V-cycle of the same {n_fine}-cell workload from the same initial state, "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cylinder_ns_mach8_131k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        raise SystemExit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_06347_amd import cgks
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    mesh, params = workload(args.workload)
+    stream = torch.cuda.current_stream()
+    solver = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, **params)
+    n_fine = mesh.n_cells
+    W0 = initial_state(solver, mesh, params)
+
+    if args.warmup > 0:
+        solver.run_cycles(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    hist = solver.run_cycles(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = n_fine * args.steps / (ms / 1e3) / 1e6
+
+    # dominant kernel: Gauss-point flux, timed with HIP events on the solver's stream
+    flux_ms, n_gp = solver.time_kernel(1, args.kernel_reps)
+    fpg = FLUX_FLOPS_PER_GP_NS if params.get("reynolds", 0.0) > 0 else FLUX_FLOPS_PER_GP_EULER
+    achieved = fpg * n_gp / (flux_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_flux<2>", "achieved": achieved,
+            "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": None,
+            "avg_ms": flux_ms, "work_items": n_gp, "flops_per_item": fpg}
+
+    out = {"metric": METRIC, "value": value, "unit": "Mcell·V-cycles/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "fine_cells": n_fine, "levels": 3,
+                      "sizes": solver.sizes, **params},
+           "roofline": roof,
+           "last_norm": float(hist[-1]) if len(hist) else None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, params, W0, n_fine)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,6 +94,8 @@ typedef struct cgks_params {
     double weno_eps;           /* nonlinear-weight epsilon, default 1e-14 */
     double lusgs_omega;        /* spectral-radius safety factor r >= |U.n| + c (Sec. 4.2), default 1 */
     double skew_limit;         /* Alg. 3 minimum sin(skewness angle), default 0.2 */
+    double slope_relax;        /* theta of the fine slope update grad <- grad + theta (grad_new - grad);
+                                  1 = full replacement (Sec. 2.4); same fixed point for any theta in (0,1] */
 } cgks_params;
 
 /* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).
@@ -126,8 +128,9 @@ void cgks_destroy(cgks_ctx* c);
 const char* cgks_last_error(const cgks_ctx* c);
 const char* cgks_strerror(int code);
 
-/* Borrow a HIP stream (a hipStream_t passed as void*); NULL selects the null
- * stream.  The library never destroys it.  Invalidates captured graphs. */
+/* Borrow a HIP stream (a hipStream_t passed as void*); NULL selects the
+ * context's own non-blocking stream.  The library never destroys a borrowed
+ * stream.  Invalidates captured graphs. */
 int cgks_set_stream(cgks_ctx* c, void* stream);
 
 /* Build the mesh hierarchy (Sec. 2.2 geometry, Sec. 3.1 reconstruction
@@ -205,6 +208,40 @@ int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double*
 /* Run n V-cycles with no host synchronisation between them (graph replay);
  * the per-cycle norms stay on the device and are returned in history. */
 int cgks_run_cycles(cgks_ctx* c, int n, double* history);
+
+/* Average duration in milliseconds of one kernel of the fine residual at the
+ * current state, timed with HIP events on the context's stream over `reps`
+ * back-to-back launches: kernel 0 = reconstruction (per cell), 1 = Gauss-point
+ * flux (per face Gauss point), 2 = gather (per cell).  The state is not
+ * modified.  Also returns the number of work items of one launch. */
+int cgks_time_kernel(cgks_ctx* c, int kernel, int reps, double* avg_ms, int64_t* work_items);
+
+/* Choose the launch shape (threads per block) of each fine-residual kernel by
+ * timing the candidates at the current state; invalidates captured graphs. */
+int cgks_autotune(cgks_ctx* c);
+/* Current launch shapes of the reconstruction, flux and gather kernels. */
+int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gather);
+
+/* Batched solves: n independent problems (each a context with its own mesh,
+ * Mach number, Reynolds number, wall temperature and angle of attack; all
+ * other parameters equal) advanced together.  The batch owns one disjoint
+ * union of the problems' hierarchies in device memory; one captured graph
+ * replay advances every problem by one V-cycle; per-problem norms are reduced
+ * in a fixed order.  The problems' fine states are copied in at creation and
+ * back by cgks_batch_solve / cgks_batch_get_state.  Problems stay owned by the
+ * caller and must outlive the batch.  CGKS_EINVAL if shared parameters differ. */
+typedef struct cgks_batch cgks_batch;
+int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out);
+int cgks_batch_autotune(cgks_batch* b);
+/* ncyc V-cycles; history (may be NULL) is [n][ncyc]. */
+int cgks_batch_run_cycles(cgks_batch* b, int ncyc, double* history);
+/* Cycles until every problem's norm <= tol (or it failed) or max_cycles.
+ * cycles_out[p]: first cycle at or below tol (else cycles run); status_out[p]:
+ * CGKS_OK, CGKS_NOTCONV or CGKS_ENONPHYS.  Returns the worst status. */
+int cgks_batch_solve(cgks_batch* b, double tol, int max_cycles, int* cycles_out, int* status_out);
+/* Copy the batch's fine states back into the problems' contexts. */
+int cgks_batch_get_state(cgks_batch* b);
+void cgks_batch_destroy(cgks_batch* b);
 
 /* Counters: positivity-guard hits of the reconstruction, prolongation skips. */
 int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);

@@ -46,6 +46,7 @@ typedef struct orc_params {
     double weno_eps;
     double lusgs_omega;
     double skew_limit;
+    double slope_relax;
 } orc_params;
 
 typedef struct orc_mesh {

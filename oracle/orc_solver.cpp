@@ -385,6 +385,14 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
     for (size_t k = 0; k < L.W.size(); ++k) L.W[k] += L.dW[k];
 }
 
+/* New slopes of the fine step: grad <- grad + theta (grad_new - grad).  theta = 1
+ * is the direct evolution of Sec. 2.4; any theta in (0,1] has the same fixed point. */
+void relax_slopes(orc_ctx* c, const std::vector<double>& gnew) {
+    std::vector<double>& g = c->lv[0].grad;
+    const double th = c->p.slope_relax;
+    for (size_t k = 0; k < g.size(); ++k) g[k] = g[k] + th * (gnew[k] - g[k]);
+}
+
 /* Explicit fine step of Eq. smo (local time step, Res = -R). */
 void fine_step(orc_ctx* c) {
     Level& L0 = c->lv[0];
@@ -393,7 +401,7 @@ void fine_step(orc_ctx* c) {
     fine_residual(c, R, g, a, dte);
     for (int i = 0; i < L0.n; ++i)
         for (int q = 0; q < nv; ++q) L0.W[i * nv + q] -= dte[i] / L0.V[i] * R[i * nv + q];
-    L0.grad = g;
+    relax_slopes(c, g);
     L0.alpha = a;
 }
 
@@ -711,7 +719,7 @@ int orc_vcycle(orc_ctx* c, double* norm_out) {
         if (s == 0 && norm_out) *norm_out = density_norm(c, R);
         for (int i = 0; i < L0.n; ++i)
             for (int q = 0; q < nv; ++q) L0.W[i * nv + q] -= dte[i] / L0.V[i] * R[i * nv + q];
-        L0.grad = g;
+        relax_slopes(c, g);
         L0.alpha = a;
     }
     for (int l = 0; l + 1 < nl; ++l) {

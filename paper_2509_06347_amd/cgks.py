@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("tau_c1", C.c_double), ("tau_c2", C.c_double),
         ("weno_gamma_large", C.c_double), ("weno_eps", C.c_double),
         ("lusgs_omega", C.c_double), ("skew_limit", C.c_double),
+        ("slope_relax", C.c_double),
     ]
 
 
@@ -76,6 +77,15 @@ _sigs = {
     "cgks_solve": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), _D, C.c_int]),
     "cgks_run_cycles": (C.c_int, [_P, C.c_int, _D]),
     "cgks_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "cgks_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, _D, C.POINTER(C.c_int64)]),
+    "cgks_autotune": (C.c_int, [_P]),
+    "cgks_launch_shapes": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cgks_batch_create": (C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P)]),
+    "cgks_batch_autotune": (C.c_int, [_P]),
+    "cgks_batch_run_cycles": (C.c_int, [_P, C.c_int, _D]),
+    "cgks_batch_solve": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cgks_batch_get_state": (C.c_int, [_P]),
+    "cgks_batch_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -268,7 +278,71 @@ class Solver:
                                          hist.ctypes.data_as(_D), max_cycles))
         return rc, hist[:ncyc.value]
 
+    def time_kernel(self, kernel, reps=20):
+        """(average ms, work items) of fine-residual kernel 0/1/2 (recon/flux/gather)."""
+        ms, n = C.c_double(), C.c_int64()
+        self._check(_lib.cgks_time_kernel(self.ctx, kernel, reps, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def autotune(self):
+        self._check(_lib.cgks_autotune(self.ctx))
+        return self.launch_shapes()
+
+    def launch_shapes(self):
+        r, f, g = C.c_int(), C.c_int(), C.c_int()
+        self._check(_lib.cgks_launch_shapes(self.ctx, C.byref(r), C.byref(f), C.byref(g)))
+        return r.value, f.value, g.value
+
     def stats(self):
         a, b = C.c_int64(), C.c_int64()
         self._check(_lib.cgks_stats(self.ctx, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+class Batch:
+    """Independent problems advanced together (see cgks_batch_* in include/cgks.h)."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (_P * len(self.solvers))(*[s.ctx for s in self.solvers])
+        h = _P()
+        rc = _lib.cgks_batch_create(len(self.solvers), arr, C.byref(h))
+        if rc != OK:
+            raise CgksError(rc, "cgks_batch_create")
+        self.h = h
+
+    def _check(self, rc):
+        if rc < 0:
+            raise CgksError(rc, "batch")
+        return rc
+
+    def autotune(self):
+        self._check(_lib.cgks_batch_autotune(self.h))
+
+    def run_cycles(self, n):
+        hist = np.zeros((len(self.solvers), n))
+        self._check(_lib.cgks_batch_run_cycles(self.h, n, hist.ctypes.data_as(_D)))
+        return hist
+
+    def solve(self, tol=1e-10, max_cycles=1000):
+        m = len(self.solvers)
+        cyc = (C.c_int * m)()
+        st = (C.c_int * m)()
+        rc = _lib.cgks_batch_solve(self.h, C.c_double(tol), max_cycles, cyc, st)
+        if rc < 0 and rc != ENONPHYS:
+            raise CgksError(rc, "cgks_batch_solve")
+        return rc, np.array(cyc[:]), np.array(st[:])
+
+    def sync_states(self):
+        self._check(_lib.cgks_batch_get_state(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.cgks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 
 #include "cgks_internal.h"
 
@@ -52,14 +53,17 @@ int d2h(cgks_ctx* c, std::vector<T>& h, const T* d, size_t count) {
     } while (0)
 
 void free_device(cgks_ctx* c) {
-    if (c->graph) hipGraphExecDestroy(c->graph);
-    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) (void)hipGraphDestroy(c->graph_tmpl);
     c->graph = nullptr;
     c->graph_tmpl = nullptr;
-    for (void* p : c->allocs) hipFree(p);
+    for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
 }
 
+}  // namespace
+
+namespace cgks {
 void make_kparams(cgks_ctx* c) {
     const cgks_params& p = c->p;
     KParams& k = c->kp;
@@ -81,6 +85,7 @@ void make_kparams(cgks_ctx* c) {
     k.g_small = 1.0 - p.weno_gamma_large;
     k.eps = p.weno_eps;
     k.omega = p.lusgs_omega;
+    k.slope_relax = p.slope_relax;
     k.df_relax = p.df_relax;
     k.df_prolong = p.df_prolong;
     const double a = p.aoa_deg * M_PI / 180.0;
@@ -88,6 +93,9 @@ void make_kparams(cgks_ctx* c) {
     k.u_inf[1] = p.mach * std::sin(a);
     k.u_inf[2] = 0.0;
 }
+}  // namespace cgks
+
+namespace {
 
 int check_level(cgks_ctx* c, int level) {
     if (!c) return CGKS_EINVAL;
@@ -168,8 +176,8 @@ void enqueue_vcycle(cgks_ctx* c) {
 int ensure_history(cgks_ctx* c, int need) {
     if (need <= c->ws.history_cap) return CGKS_OK;
     /* the captured graph refers to the old buffer */
-    if (c->graph) hipGraphExecDestroy(c->graph);
-    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) (void)hipGraphDestroy(c->graph_tmpl);
     c->graph = nullptr;
     c->graph_tmpl = nullptr;
     int cap = std::max(need, 2 * c->ws.history_cap);
@@ -178,6 +186,17 @@ int ensure_history(cgks_ctx* c, int need) {
     c->ws.history = h;
     c->ws.history_cap = cap;
     return CGKS_OK;
+}
+
+}  // namespace
+
+namespace cgks {
+
+void invalidate_graph(cgks_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) (void)hipGraphDestroy(c->graph_tmpl);
+    c->graph = nullptr;
+    c->graph_tmpl = nullptr;
 }
 
 int build_graph(cgks_ctx* c) {
@@ -190,6 +209,10 @@ int build_graph(cgks_ctx* c) {
     HIPCHK(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
     return CGKS_OK;
 }
+
+}  // namespace cgks
+
+namespace {
 
 int restore_saved(cgks_ctx* c) {
     FineDev& f = c->fine;
@@ -392,6 +415,7 @@ void cgks_default_params(cgks_params* p) {
     p->weno_eps = 1e-14;
     p->lusgs_omega = 1.0;
     p->skew_limit = 0.2;
+    p->slope_relax = 1.0;
 }
 
 const char* cgks_strerror(int code) {
@@ -414,14 +438,15 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (p->dim != 2 && p->dim != 3) return CGKS_EINVAL;
     if (p->n_post != 0 || p->n_pre_fine < 1 || p->n_sweeps < 0 || !(p->mach > 0.0) || !(p->gamma > 1.0))
         return CGKS_EINVAL;
-    if (p->precision != CGKS_FP64) return CGKS_EINVAL;
+    if (p->precision != CGKS_FP64 && p->precision != CGKS_MIXED) return CGKS_EINVAL;
+    if (!(p->slope_relax > 0.0 && p->slope_relax <= 1.0)) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
     c->p = *p;
     c->dim = p->dim;
     c->nv = p->dim + 2;
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return CGKS_EDEVICE;
@@ -434,17 +459,17 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
 
 void cgks_destroy(cgks_ctx* c) {
     if (!c) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_device(c);
-    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
 
 int cgks_set_stream(cgks_ctx* c, void* stream) {
     if (!c) return CGKS_EINVAL;
     c->stream = stream ? (hipStream_t)stream : c->own_stream;
-    if (c->graph) hipGraphExecDestroy(c->graph);
-    if (c->graph_tmpl) hipGraphDestroy(c->graph_tmpl);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_tmpl) (void)hipGraphDestroy(c->graph_tmpl);
     c->graph = nullptr;
     c->graph_tmpl = nullptr;
     return CGKS_OK;
@@ -717,6 +742,28 @@ int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double*
     return CGKS_NOTCONV;
 }
 
+int cgks_time_kernel(cgks_ctx* c, int kernel, int reps, double* avg_ms, int64_t* work_items) {
+    TRY(check_level(c, 0));
+    if (kernel < 0 || kernel > 2 || reps <= 0) return fail(c, CGKS_EINVAL, "kernel must be 0..2 and reps > 0");
+    /* inputs of the later kernels come from the earlier ones */
+    for (int k = 0; k < kernel; ++k) launch_fine_kernel(c, k);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    launch_fine_kernel(c, kernel);   /* warm-up */
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch_fine_kernel(c, kernel);
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (avg_ms) *avg_ms = ms / reps;
+    if (work_items) *work_items = (kernel == 1) ? (int64_t)c->fine.nf * c->fine.ngp : (int64_t)c->fine.n;
+    return CGKS_OK;
+}
+
 int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
     TRY(check_level(c, 0));
     unsigned long long g = 0, s = 0;
@@ -725,6 +772,336 @@ int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
     if (guard_hits) *guard_hits = (int64_t)g;
     if (prolong_skips) *prolong_skips = (int64_t)s;
     return CGKS_OK;
+}
+
+}  // extern "C"
+
+/* ------------------------------------------------------------- autotune --- */
+
+extern "C" int cgks_autotune(cgks_ctx* c) {
+    TRY(check_level(c, 0));
+    /* launch shape of each fine kernel: the fastest candidate at the current state */
+    static const int cand[3][3] = {{64, 128, 0}, {64, 128, 256}, {64, 128, 256}};
+    int best[3] = {c->blk_recon, c->blk_flux, c->blk_gather};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int which = 0; which < 3; ++which) {
+        float tbest = 1e30f;
+        for (int j = 0; j < 3 && cand[which][j]; ++j) {
+            const int b = cand[which][j];
+            for (int k = 0; k < which; ++k) launch_fine_kernel(c, k, 0);
+            launch_fine_kernel(c, which, b);
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 5; ++r) launch_fine_kernel(c, which, b);
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < tbest) {
+                tbest = ms;
+                best[which] = b;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->blk_recon = best[0];
+    c->blk_flux = best[1];
+    c->blk_gather = best[2];
+    invalidate_graph(c);
+    return CGKS_OK;
+}
+
+extern "C" int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gather) {
+    if (!c) return CGKS_EINVAL;
+    if (recon) *recon = c->blk_recon;
+    if (flux) *flux = c->blk_flux;
+    if (gather) *gather = c->blk_gather;
+    return CGKS_OK;
+}
+
+/* --------------------------------------------------------------- batches --- */
+
+struct cgks_batch {
+    std::vector<cgks_ctx*> probs;
+    cgks_ctx* m = nullptr;                 /* merged (disjoint-union) context */
+    std::vector<std::vector<int>> coff;    /* [level][b] cell offsets, size nprob+1 */
+    int cap = 256;
+};
+
+namespace {
+
+bool same_shared_params(const cgks_params& a, const cgks_params& b) {
+    return a.dim == b.dim && a.gamma == b.gamma && a.prandtl == b.prandtl &&
+           a.sutherland_S_ratio == b.sutherland_S_ratio && a.cfl_exp == b.cfl_exp && a.cfl_imp == b.cfl_imp &&
+           a.n_levels == b.n_levels && a.n_pre_fine == b.n_pre_fine && a.n_post == b.n_post &&
+           a.n_sweeps == b.n_sweeps && a.df_relax == b.df_relax && a.df_prolong == b.df_prolong &&
+           a.precision == b.precision && a.tau_c1 == b.tau_c1 && a.tau_c2 == b.tau_c2 &&
+           a.weno_gamma_large == b.weno_gamma_large && a.weno_eps == b.weno_eps &&
+           a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
+           ((a.reynolds > 0.0) == (b.reynolds > 0.0));
+}
+
+/* Copy a [rows][n_b] SoA block between a problem and the merged arrays. */
+int copy_rows(cgks_ctx* c, double* dst, size_t dpitch, const double* src, size_t spitch, size_t n, size_t rows) {
+    HIPCHK(hipMemcpy2DAsync(dst, dpitch * sizeof(double), src, spitch * sizeof(double), n * sizeof(double), rows,
+                            hipMemcpyDeviceToDevice, c->stream));
+    return CGKS_OK;
+}
+
+int batch_state(cgks_batch* B, bool to_merged) {
+    cgks_ctx* m = B->m;
+    const size_t N = m->fine.n, nv = m->nv, dim = m->dim;
+    for (size_t b = 0; b < B->probs.size(); ++b) {
+        cgks_ctx* p = B->probs[b];
+        const size_t off = B->coff[0][b], n = p->fine.n;
+        struct { double* pm; double* pp; size_t rows; } arr[3] = {
+            {m->fine.W + off, p->fine.W, nv}, {m->fine.grad + off, p->fine.grad, nv * dim}, {m->fine.alpha + off, p->fine.alpha, 1}};
+        for (auto& a : arr) {
+            if (to_merged) TRY(copy_rows(m, a.pm, N, a.pp, n, n, a.rows));
+            else TRY(copy_rows(m, a.pp, n, a.pm, N, n, a.rows));
+        }
+    }
+    cgks_ctx* c = m;
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return CGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out) {
+    if (n <= 0 || !probs || !out) return CGKS_EINVAL;
+    *out = nullptr;
+    for (int b = 0; b < n; ++b) {
+        if (!probs[b] || !probs[b]->have_mesh) return CGKS_EINVAL;
+        if (!same_shared_params(probs[0]->p, probs[b]->p)) return CGKS_EINVAL;
+    }
+    cgks_batch* B = new cgks_batch();
+    B->probs.assign(probs, probs + n);
+    cgks_ctx* m = new cgks_ctx();
+    B->m = m;
+    m->p = probs[0]->p;
+    m->dim = probs[0]->dim;
+    m->nv = probs[0]->nv;
+    (void)hipGetDevice(&m->device);
+    if (hipStreamCreateWithFlags(&m->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        cgks_batch_destroy(B);
+        return CGKS_EDEVICE;
+    }
+    m->stream = m->own_stream;
+    make_kparams(m);
+    const int L = m->p.n_levels, dim = m->dim;
+    m->hl.assign(L, HLevel());
+    B->coff.assign(L, std::vector<int>(n + 1, 0));
+    for (int l = 0; l < L; ++l)
+        for (int b = 0; b < n; ++b) B->coff[l][b + 1] = B->coff[l][b] + probs[b]->hl[l].n;
+    for (int l = 0; l < L; ++l) {
+        HLevel& M = m->hl[l];
+        M.n = B->coff[l][n];
+        int fo = 0;
+        for (int b = 0; b < n; ++b) {
+            const HLevel& H = probs[b]->hl[l];
+            const int co = B->coff[l][b];
+            M.V.insert(M.V.end(), H.V.begin(), H.V.end());
+            M.C.insert(M.C.end(), H.C.begin(), H.C.end());
+            for (HFace f : H.faces) {
+                f.L += co;
+                if (f.R >= 0) f.R += co;
+                M.faces.push_back(f);
+            }
+            for (const auto& lst : H.cf) {
+                std::vector<int> v(lst);
+                for (int& x : v) x += fo;
+                M.cf.push_back(v);
+            }
+            fo += (int)H.faces.size();
+            M.color.insert(M.color.end(), H.color.begin(), H.color.end());
+            M.ncolor = std::max(M.ncolor, H.ncolor);
+            M.nslot = std::max(M.nslot, H.nslot);
+            if (l + 1 < L)
+                for (int x : H.parent) M.parent.push_back(x + B->coff[l + 1][b]);
+            if (l > 0)
+                for (const auto& ch : H.children) {
+                    std::vector<int> v(ch);
+                    for (int& x : v) x += B->coff[l - 1][b];
+                    M.children.push_back(v);
+                }
+            if (l == 0) {
+                M.h.insert(M.h.end(), H.h.begin(), H.h.end());
+                M.nbasis.insert(M.nbasis.end(), H.nbasis.begin(), H.nbasis.end());
+            }
+        }
+        if (l == 0) {
+            /* SoA re-layout of the per-cell operator and basis means */
+            const size_t N = M.n;
+            const size_t nq = (dim == 2) ? 5 : 9, ncol = (size_t)(dim + 1) * (1 + dim);
+            M.mean0.assign(nq * N, 0.0);
+            M.op.assign(nq * ncol * N, 0.0);
+            for (int b = 0; b < n; ++b) {
+                const HLevel& H = probs[b]->hl[0];
+                const size_t nb = H.n, co = B->coff[0][b];
+                for (size_t r = 0; r < nq; ++r)
+                    std::copy(H.mean0.begin() + r * nb, H.mean0.begin() + (r + 1) * nb, M.mean0.begin() + r * N + co);
+                for (size_t r = 0; r < nq * ncol; ++r)
+                    std::copy(H.op.begin() + r * nb, H.op.begin() + (r + 1) * nb, M.op.begin() + r * N + co);
+            }
+        }
+        M.perm.resize(M.n);
+        for (int i = 0; i < M.n; ++i) M.perm[i] = i;
+        if (l > 0)
+            std::stable_sort(M.perm.begin(), M.perm.end(), [&](int a, int b2) { return M.color[a] < M.color[b2]; });
+        M.iperm.resize(M.n);
+        for (int i = 0; i < M.n; ++i) M.iperm[M.perm[i]] = i;
+        M.color_off.assign(M.ncolor + 1, 0);
+        for (int i = 0; i < M.n; ++i) M.color_off[M.color[i]]++;
+        for (int k = 1; k <= M.ncolor; ++k) M.color_off[k] += M.color_off[k - 1];
+    }
+    cgks_ctx* c = m;  /* for the HIPCHK / TRY macros */
+    int rc = upload(m);
+    if (rc) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    m->have_mesh = true;
+    /* problem ids and the per-problem parameter table */
+    std::vector<double> tab((size_t)PTAB * n);
+    for (int b = 0; b < n; ++b) {
+        const KParams& k = probs[b]->kp;
+        const double t[PTAB] = {k.mach, k.reynolds, k.mu_inf, k.Tw, k.u_inf[0], k.u_inf[1], k.u_inf[2]};
+        for (int j = 0; j < PTAB; ++j) tab[(size_t)PTAB * b + j] = t[j];
+    }
+    auto owner = [&](int l, int orig) {
+        return (int)(std::upper_bound(B->coff[l].begin(), B->coff[l].end(), orig) - B->coff[l].begin()) - 1;
+    };
+    double* dtab;
+    int *pid, *fpid, *poff;
+    double* r2;
+    if ((rc = dalloc(c, &dtab, tab.size())) || (rc = h2d(c, dtab, tab))) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    std::vector<int> hp(m->hl[0].n), hf(m->hl[0].faces.size());
+    for (int i = 0; i < m->hl[0].n; ++i) hp[i] = owner(0, i);
+    for (size_t f = 0; f < hf.size(); ++f) hf[f] = owner(0, m->hl[0].faces[f].L);
+    if ((rc = dalloc(c, &pid, hp.size())) || (rc = h2d(c, pid, hp)) || (rc = dalloc(c, &fpid, hf.size())) ||
+        (rc = h2d(c, fpid, hf)) || (rc = dalloc(c, &poff, n + 1)) || (rc = h2d(c, poff, B->coff[0])) ||
+        (rc = dalloc(c, &r2, m->hl[0].n))) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    m->fine.pid = pid;
+    m->fine.fpid = fpid;
+    m->fine.ptab = dtab;
+    m->fine.r2 = r2;
+    for (int l = 1; l < L; ++l) {
+        const HLevel& H = m->hl[l];
+        std::vector<int> cp(H.n);
+        for (int I = 0; I < H.n; ++I) cp[I] = owner(l, H.perm[I]);
+        int* d;
+        if ((rc = dalloc(c, &d, cp.size())) || (rc = h2d(c, d, cp))) {
+            cgks_batch_destroy(B);
+            return rc;
+        }
+        m->coarse[l - 1].pid = d;
+        m->coarse[l - 1].ptab = dtab;
+    }
+    m->ws.nprob = n;
+    m->ws.poff = poff;
+    m->ws.ptab = dtab;
+    double* hist;
+    if ((rc = dalloc(c, &hist, (size_t)n * B->cap))) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    m->ws.history = hist;
+    m->ws.history_cap = B->cap;
+    if ((rc = batch_state(B, true))) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return CGKS_OK;
+}
+
+int cgks_batch_autotune(cgks_batch* B) {
+    if (!B) return CGKS_EINVAL;
+    return cgks_autotune(B->m);
+}
+
+int cgks_batch_run_cycles(cgks_batch* B, int ncyc, double* history) {
+    if (!B || ncyc < 0) return CGKS_EINVAL;
+    cgks_ctx* c = B->m;
+    const int n = (int)B->probs.size();
+    TRY(build_graph(c));
+    std::vector<double> h((size_t)n * B->cap);
+    int done = 0;
+    while (done < ncyc) {
+        const int k = std::min(B->cap, ncyc - done);
+        TRY(set_counters(c));
+        for (int j = 0; j < k; ++j) HIPCHK(hipGraphLaunch(c->graph, c->stream));
+        if (history) {
+            HIPCHK(hipMemcpyAsync(h.data(), c->ws.history, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (int b = 0; b < n; ++b)
+                for (int j = 0; j < k; ++j) history[(size_t)b * ncyc + done + j] = h[(size_t)b * B->cap + j];
+        }
+        done += k;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CGKS_OK;
+}
+
+int cgks_batch_solve(cgks_batch* B, double tol, int max_cycles, int* cycles_out, int* status_out) {
+    if (!B || max_cycles < 0) return CGKS_EINVAL;
+    cgks_ctx* c = B->m;
+    const int n = (int)B->probs.size();
+    TRY(build_graph(c));
+    std::vector<int> conv(n, -1), bad(n, 0);
+    std::vector<double> h((size_t)n * B->cap);
+    int done = 0, chunk = 8;
+    while (done < max_cycles) {
+        const int k = std::min(std::min(chunk, B->cap), max_cycles - done);
+        TRY(set_counters(c));
+        for (int j = 0; j < k; ++j) HIPCHK(hipGraphLaunch(c->graph, c->stream));
+        HIPCHK(hipMemcpyAsync(h.data(), c->ws.history, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool all = true;
+        for (int b = 0; b < n; ++b) {
+            for (int j = 0; j < k; ++j) {
+                const double v = h[(size_t)b * B->cap + j];
+                if (!std::isfinite(v)) bad[b] = 1;
+                if (conv[b] < 0 && v <= tol) conv[b] = done + j + 1;
+            }
+            if (conv[b] < 0 && !bad[b]) all = false;
+        }
+        done += k;
+        if (all) break;
+        chunk = std::min(64, chunk * 2);
+    }
+    TRY(batch_state(B, false));
+    int rc = CGKS_OK;
+    for (int b = 0; b < n; ++b) {
+        if (cycles_out) cycles_out[b] = conv[b] >= 0 ? conv[b] : done;
+        const int s = bad[b] ? CGKS_ENONPHYS : (conv[b] >= 0 ? CGKS_OK : CGKS_NOTCONV);
+        if (status_out) status_out[b] = s;
+        if (s == CGKS_ENONPHYS) rc = CGKS_ENONPHYS;
+        else if (s == CGKS_NOTCONV && rc == CGKS_OK) rc = CGKS_NOTCONV;
+    }
+    return rc;
+}
+
+int cgks_batch_get_state(cgks_batch* B) {
+    if (!B) return CGKS_EINVAL;
+    return batch_state(B, false);
+}
+
+void cgks_batch_destroy(cgks_batch* B) {
+    if (!B) return;
+    if (B->m) cgks_destroy(B->m);
+    delete B;
 }
 
 }  // extern "C"

@@ -64,6 +64,10 @@ struct FineDev {
     double *R, *gnew, *anew, *dt, *dti;
     double *res;                      /* -R of the restriction evaluation */
     unsigned long long* guard;        /* positivity-guard hit counter */
+    /* batched solves: problem id per cell / per face and the per-problem table */
+    const int *pid, *fpid;
+    const double* ptab;
+    double* r2;                       /* per-cell (R_rho / V)^2 for per-problem norms */
 };
 
 struct CoarseDev {
@@ -75,7 +79,12 @@ struct CoarseDev {
     double *W, *W0, *F, *Rstar, *alpha, *dW, *rhs, *D, *r, *dte, *dti;
     int *parent;                      /* of the finer level's internal cells: this level's internal index */
     int *child_off, *child;           /* CSR of finer internal indices */
+    const int* pid;                   /* batched solves: problem id per cell (else null) */
+    const double* ptab;
 };
+
+/* Per-problem entries of a batched solve (the fields that may differ). */
+constexpr int PTAB = 7;               /* mach, reynolds, mu_inf, Tw, u_inf[3] */
 
 struct Workspace {
     double* partial = nullptr;        /* per-block norm partial sums */
@@ -85,13 +94,17 @@ struct Workspace {
     int* counter = nullptr;           /* device cycle counter */
     unsigned long long* skips = nullptr;
     int* status = nullptr;            /* non-physical flag */
+    /* batched solves */
+    int nprob = 0;
+    int* poff = nullptr;              /* fine-cell offsets of the problems, nprob+1 */
+    double* ptab = nullptr;           /* per-problem parameter table */
 };
 
 /* Scalar parameters as seen by the kernels. */
 struct KParams {
     int dim;
     double gamma, K, prandtl, mach, reynolds, mu_inf, Tinf, S_suth, Tw;
-    double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega;
+    double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax;
     int df_relax, df_prolong;
     double u_inf[3];
 };
@@ -116,18 +129,24 @@ struct cgks_ctx {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_tmpl = nullptr;
     int cycles_done = 0;
+    /* launch shapes chosen by the autotuner */
+    int blk_recon = 128, blk_flux = 256, blk_gather = 256;
 };
 
 namespace cgks {
 int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* const* parent);
 int agglomerate_level(const cgks_ctx* c, int level, std::vector<int>& agg);
 int upload(cgks_ctx* c);
+void make_kparams(cgks_ctx* c);
+void invalidate_graph(cgks_ctx* c);
+int build_graph(cgks_ctx* c);
 int fail(cgks_ctx* c, int code, const std::string& msg);
 int hip_fail(cgks_ctx* c, hipError_t e, const char* what);
 
 /* kernel launchers (kernels_fine.hip / kernels_coarse.hip) */
 void launch_fine_residual(cgks_ctx* c, int mode);
 void launch_fine_recon(cgks_ctx* c);
+void launch_fine_kernel(cgks_ctx* c, int which, int block = 0);
 void launch_coarse_rhs(cgks_ctx* c, int level, int mode);
 void launch_lusgs(cgks_ctx* c, int level);
 void launch_restrict(cgks_ctx* c, int level);

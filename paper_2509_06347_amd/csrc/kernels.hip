@@ -29,6 +29,23 @@ namespace cgks {
 
 constexpr int BLOCK = 256;
 
+/* Parameters of the problem that owns item idx (batched solves); the shared
+ * parameters come from kp itself. */
+__device__ __forceinline__ KParams localize(const KParams& kp, const double* ptab, const int* pid, int idx) {
+    KParams k = kp;
+    if (pid) {
+        const double* t = ptab + PTAB * pid[idx];
+        k.mach = t[0];
+        k.reynolds = t[1];
+        k.mu_inf = t[2];
+        k.Tw = t[3];
+        k.u_inf[0] = t[4];
+        k.u_inf[1] = t[5];
+        k.u_inf[2] = t[6];
+    }
+    return k;
+}
+
 template <int D>
 struct Shape {
     static constexpr int NV = D + 2;
@@ -98,13 +115,21 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
     }
 }
 
+constexpr int RBLOCK = 128;   /* reconstruction block: per-thread LDS columns */
+
 template <int D>
-__global__ void __launch_bounds__(BLOCK) k_recon(FineDev f, KParams kp) {
+__global__ void __launch_bounds__(RBLOCK) k_recon(FineDev f, KParams kp0) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NC = S::NC, NCOL = S::NCOL;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NK = NQ + D;                    /* coefficients per component */
+    /* Polynomial coefficients live in LDS, one column per thread (no sharing, no
+     * barriers): keeps the kernel free of register spills. */
+    __shared__ double sc[NV * NK][RBLOCK];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + t;
     const int n = f.n, nf = f.nf;
     if (i >= n) return;
+    const KParams kp = localize(kp0, f.ptab, f.pid, i);
     double W0[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) W0[q] = f.W[q * n + i];
@@ -159,36 +184,33 @@ __global__ void __launch_bounds__(BLOCK) k_recon(FineDev f, KParams kp) {
             ghost_state<D, false>(kp, tag[s], W0, nullptr, nout[s], Wn[s], nullptr);
         }
     }
-
     double mean[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) mean[k] = f.mean0[k * n + i];
 
-    /* per-component polynomial: P = Q0 + sum c2_k (phi_k - mean_k) + c1 . (x - xc) / h */
-    double c2[NV][NQ], c1[NV][D];
+    /* per component: p^2 coefficients a, Green-Gauss gradient g (times h), weights;
+     * P = Q0 + sum_k c2_k (phi_k - mean_k) + sum_d c1_d X_d with X = (x - xc)/h */
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        double in[NCOL];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (nbr[s] >= 0) {
-                in[s * (1 + D)] = Wn[s][q] - W0[q];
-#pragma unroll
-                for (int d = 0; d < D; ++d) in[s * (1 + D) + 1 + d] = f.grad[(q * D + d) * n + nbr[s]];
-            } else {
-#pragma unroll
-                for (int d = 0; d <= D; ++d) in[s * (1 + D) + d] = 0.0;
-            }
-        }
         double a[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            double acc = 0.0;
+        for (int k = 0; k < NQ; ++k) a[k] = 0.0;
 #pragma unroll
-            for (int j = 0; j < NCOL; ++j) acc += f.op[(k * NCOL + j) * n + i] * in[j];
-            a[k] = acc;
+        for (int s = 0; s < NS; ++s) {
+            if (nbr[s] < 0) continue;
+            const double dq = Wn[s][q] - W0[q];
+            double gs[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) gs[d] = f.grad[(q * D + d) * n + nbr[s]];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const double* o = f.op + (size_t)(k * NCOL + s * (1 + D)) * n + i;
+                double acc = o[0] * dq;
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc += o[(size_t)(1 + d) * n] * gs[d];
+                a[k] += acc;
+            }
         }
-        /* Green-Gauss gradient times h (scaled coordinates), alpha-scaled */
         double g[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) g[d] = 0.0;
@@ -212,12 +234,13 @@ __global__ void __launch_bounds__(BLOCK) k_recon(FineDev f, KParams kp) {
         const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
         const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) c2[q][k] = cp2 * a[k];
+        for (int k = 0; k < NQ; ++k) sc[q * NK + k][t] = cp2 * a[k];
 #pragma unroll
-        for (int d = 0; d < D; ++d) c1[q][d] = cp1 * g[d];
+        for (int d = 0; d < D; ++d) sc[q * NK + NQ + d][t] = cp1 * g[d];
     }
 
     const double ih = 1.0 / h;
+    /* value (and gradient) of the reconstruction at x */
     auto eval = [&](const double* x, double* Wx, double (*gx)[D], bool grad) {
         double X[3], phi[NQ], dphi[NQ][3];
 #pragma unroll
@@ -227,16 +250,16 @@ __global__ void __launch_bounds__(BLOCK) k_recon(FineDev f, KParams kp) {
         for (int q = 0; q < NV; ++q) {
             double v = W0[q];
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) v += c2[q][k] * (phi[k] - mean[k]);
+            for (int k = 0; k < NQ; ++k) v += sc[q * NK + k][t] * (phi[k] - mean[k]);
 #pragma unroll
-            for (int d = 0; d < D; ++d) v += c1[q][d] * X[d];
+            for (int d = 0; d < D; ++d) v += sc[q * NK + NQ + d][t] * X[d];
             Wx[q] = v;
             if (grad) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    double gd = c1[q][d];
+                    double gd = sc[q * NK + NQ + d][t];
 #pragma unroll
-                    for (int k = 0; k < NQ; ++k) gd += c2[q][k] * dphi[k][d];
+                    for (int k = 0; k < NQ; ++k) gd += sc[q * NK + k][t] * dphi[k][d];
                     gx[q][d] = gd * ih;
                 }
             }
@@ -298,13 +321,14 @@ __global__ void __launch_bounds__(BLOCK) k_recon(FineDev f, KParams kp) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(BLOCK) k_flux(FineDev f, KParams kp) {
+__global__ void __launch_bounds__(BLOCK) k_flux(FineDev f, KParams kp0) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NG = S::NG, NC = S::NC;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int nf = f.nf;
     if (t >= NG * nf) return;
     const int k = t / nf, fc = t - k * nf;
+    const KParams kp = localize(kp0, f.ptab, f.fpid, fc);
     double WL[NV], WR[NV], gL[NV][D], gR[NV][D], nn[D];
     const double* sL = f.gpst + (size_t)((0 * NG + k) * NC) * nf + fc;
     const double* sR = f.gpst + (size_t)((1 * NG + k) * NC) * nf + fc;
@@ -401,13 +425,17 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
             f.alpha[i] = a;
         } else {
             const double dtv = f.dt[i] / V;
+            const double th = kp.slope_relax;
             double Wn[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 Wn[q] = f.W[q * n + i] - dtv * R[q];
                 f.W[q * n + i] = Wn[q];
 #pragma unroll
-                for (int d = 0; d < D; ++d) f.grad[(q * D + d) * n + i] = sc * Gs[q][d];
+                for (int d = 0; d < D; ++d) {
+                    const double go = f.grad[(q * D + d) * n + i];
+                    f.grad[(q * D + d) * n + i] = go + th * (sc * Gs[q][d] - go);
+                }
             }
             f.alpha[i] = a;
             Prim P;
@@ -416,10 +444,11 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
             if (mode == FINE_STEP_NORM) {
                 const double r = R[0] / V;
                 contrib = r * r;
+                if (f.pid) f.r2[i] = contrib;
             }
         }
     }
-    if (mode == FINE_STEP_NORM) {
+    if (mode == FINE_STEP_NORM && !f.pid) {
         const double s = block_sum(contrib);
         if (threadIdx.x == 0) partial[blockIdx.x] = s;
     }
@@ -439,14 +468,35 @@ __global__ void __launch_bounds__(BLOCK) k_norm_finalize(const double* partial, 
     }
 }
 
+/* Per-problem norms of a batched solve: block b reduces the cells of problem b
+ * in a fixed order and appends its norm to history[b * cap + cycle]. */
+__global__ void __launch_bounds__(BLOCK) k_norm_batch(const double* r2, const int* off, const double* ptab,
+                                                      double* history, int cap, int* counter, int nprob) {
+    const int b = blockIdx.x;
+    const int lo = off[b], hi = off[b + 1];
+    double v = 0.0;
+    for (int k = lo + threadIdx.x; k < hi; k += BLOCK) v += r2[k];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) {
+        const int c = *counter;
+        const double nrm = sqrt(s / (hi - lo)) / ptab[PTAB * b];
+        if (c < cap) history[(size_t)b * cap + c] = nrm;
+    }
+}
+
+__global__ void k_count(int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
+}
+
 /* ----------------------------------------------------------------- coarse --- */
 
-template <int D>
-__global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp, int mode) {
+template <int D, class T>
+__global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp0, int mode) {
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
     if (I >= n) return;
+    const KParams kp = localize(kp0, c.ptab, c.pid, I);
     double W[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) W[q] = c.W[q * n + I];
@@ -494,14 +544,14 @@ __global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp, i
         }
         double r = kp.omega * (fabs(umn) + sqrt(kp.gamma * Pm.p / Pm.rho));
         if (kp.reynolds > 0.0) r += 2.0 * visc * sutherland(kp, Pm.p / Pm.rho) / (Pm.rho * dist);
-        c.r[s * n + I] = r;
+        reinterpret_cast<T*>(c.r)[s * n + I] = (T)r;
         sr += S * r;
         lam += S * (fabs(un) + cs);
         s2 += S * S;
     }
     if (mode == COARSE_FORCING) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) c.F[q * n + I] = c.Rstar[q * n + I] - Res[q];
+        for (int q = 0; q < NV; ++q) c.F[q * n + I] = (double)reinterpret_cast<const T*>(c.Rstar)[q * n + I] - Res[q];
         return;
     }
     if (kp.reynolds > 0.0) lam += visc * sutherland(kp, P.p / P.rho) / P.rho * s2 / c.V[I];
@@ -515,88 +565,144 @@ __global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp, i
     c.D[I] = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
 }
 
+/* Increment of the normal Euler flux T(W + dW) - T(W).  In FP64 it is the
+ * literal difference; in FP32 it is written in terms of the increments so no
+ * two large, nearly equal numbers are subtracted (base state from FP64). */
+template <int D, class T>
+__device__ __forceinline__ void flux_increment(const KParams& kp, const double* W, const T* dW, const T* n, T* dT) {
+    constexpr int NV = D + 2;
+    if constexpr (sizeof(T) == sizeof(double)) {
+        double Wp[NV], T1[NV], T0[NV], nn[D];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wp[q] = W[q] + dW[q];
+#pragma unroll
+        for (int d = 0; d < D; ++d) nn[d] = n[d];
+        euler_flux<D>(kp, Wp, nn, T1);
+        euler_flux<D>(kp, W, nn, T0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dT[q] = T1[q] - T0[q];
+    } else {
+        double ke = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ke += W[1 + d] * W[1 + d];
+        const double pd = (kp.gamma - 1.0) * (W[D + 1] - 0.5 * ke / W[0]);
+        const T r = (T)W[0], E = (T)W[D + 1], p = (T)pd, dr = dW[0], dE = dW[D + 1];
+        T m[D], dm[D], mn = 0, dmn = 0, m2 = 0, mdm = 0, dm2 = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            m[d] = (T)W[1 + d];
+            dm[d] = dW[1 + d];
+            mn += m[d] * n[d];
+            dmn += dm[d] * n[d];
+            m2 += m[d] * m[d];
+            mdm += m[d] * dm[d];
+            dm2 += dm[d] * dm[d];
+        }
+        const T inv = (T)1 / (r * (r + dr));
+        /* d(X m_n / rho) for a quantity X with increment dX */
+        auto dq = [&](T X, T dX) { return (r * (X * dmn + dX * mn + dX * dmn) - dr * X * mn) * inv; };
+        const T dke = (r * ((T)2 * mdm + dm2) - dr * m2) * inv;            /* d(|m|^2 / rho) */
+        const T dp = (T)(kp.gamma - 1.0) * (dE - (T)0.5 * dke);
+        dT[0] = dmn;
+#pragma unroll
+        for (int d = 0; d < D; ++d) dT[1 + d] = dq(m[d], dm[d]) + dp * n[d];
+        dT[D + 1] = dq(E + p, dE + dp);
+    }
+}
+
 /* One colour of the forward (fwd = 1) or backward sweep (Eqs. gpu-forward/
  * backward-relaxation).  Cells of colour c occupy [lo, hi); lower colours sit
- * below lo and higher colours at or above hi. */
-template <int D>
+ * below lo and higher colours at or above hi.  T is the type of the
+ * correction arithmetic: double (FP64) or float (mixed precision). */
+template <int D, class T>
 __global__ void __launch_bounds__(BLOCK) k_lusgs(CoarseDev c, KParams kp, int lo, int hi, int fwd) {
     constexpr int NV = D + 2;
     const int I = lo + blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
     if (I >= hi) return;
-    double acc[NV];
+    T* dW = reinterpret_cast<T*>(c.dW);
+    const T* rr = reinterpret_cast<const T*>(c.r);
+    T acc[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NV; ++q) acc[q] = 0;
     for (int s = 0; s < c.nslot; ++s) {
         const int J = c.snbr[s * n + I];
         if (J < 0) continue;
         if (fwd ? (J >= lo) : (J < hi)) continue;
-        const double S = c.sS[s * n + I], r = c.r[s * n + I];
-        double nn[D], WJ[NV], dJ[NV], Wp[NV], T1[NV], T0[NV];
+        const T S = (T)c.sS[s * n + I], r = rr[s * n + I];
+        T nn[D], dJ[NV], dT[NV];
+        double WJ[NV];
 #pragma unroll
-        for (int d = 0; d < D; ++d) nn[d] = c.sn[(d * c.nslot + s) * n + I];
+        for (int d = 0; d < D; ++d) nn[d] = (T)c.sn[(d * c.nslot + s) * n + I];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             WJ[q] = c.W[q * n + J];
-            dJ[q] = c.dW[q * n + J];
-            Wp[q] = WJ[q] + dJ[q];
+            dJ[q] = dW[q * n + J];
         }
-        euler_flux<D>(kp, Wp, nn, T1);
-        euler_flux<D>(kp, WJ, nn, T0);
+        flux_increment<D, T>(kp, WJ, dJ, nn, dT);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) acc[q] += S * (T1[q] - T0[q] - r * dJ[q]);
+        for (int q = 0; q < NV; ++q) acc[q] += S * (dT[q] - r * dJ[q]);
     }
-    const double a = kp.df_relax ? c.alpha[I] : 1.0;
-    const double Di = c.D[I];
+    const T a = kp.df_relax ? (T)c.alpha[I] : (T)1;
+    const T Di = (T)c.D[I];
     if (fwd) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) c.dW[q * n + I] = (c.rhs[q * n + I] - 0.5 * a * acc[q]) / Di;
+        for (int q = 0; q < NV; ++q) dW[q * n + I] = ((T)c.rhs[q * n + I] - (T)0.5 * a * acc[q]) / Di;
     } else {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) c.dW[q * n + I] -= 0.5 * a * acc[q] / Di;
+        for (int q = 0; q < NV; ++q) dW[q * n + I] -= (T)0.5 * a * acc[q] / Di;
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_add(double* W, const double* dW, int m) {
+template <class T>
+__global__ void __launch_bounds__(BLOCK) k_add(double* W, const double* dWraw, int m) {
+    const T* dW = reinterpret_cast<const T*>(dWraw);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < m) W[t] += dW[t];
+    if (t < m) W[t] += (double)dW[t];
 }
 
-/* Restriction (Sec. 5.2): W0 = sum V W / V_c, Res* = sum Res, alpha = min. */
-template <int D>
+/* Restriction (Sec. 5.2): W0 = sum V W / V_c (FP64), Res* = sum Res (in T),
+ * alpha = min. */
+template <int D, class T>
 __global__ void __launch_bounds__(BLOCK) k_restrict(CoarseDev c, const double* Wf, const double* Vf,
                                                    const double* resf, const double* af, int nfine) {
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
     if (I >= n) return;
-    double w[NV], r[NV], amin = 1.0e300;
+    double w[NV], amin = 1.0e300;
+    T r[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) w[q] = r[q] = 0.0;
+    for (int q = 0; q < NV; ++q) {
+        w[q] = 0.0;
+        r[q] = 0;
+    }
     for (int k = c.child_off[I]; k < c.child_off[I + 1]; ++k) {
         const int i = c.child[k];
         const double v = Vf[i];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             w[q] += v * Wf[q * nfine + i];
-            r[q] += resf[q * nfine + i];
+            r[q] += (T)resf[q * nfine + i];
         }
         amin = fmin(amin, af[i]);
     }
     const double iv = 1.0 / c.V[I];
+    T* Rs = reinterpret_cast<T*>(c.Rstar);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         const double w0 = w[q] * iv;
         c.W0[q * n + I] = w0;
         c.W[q * n + I] = w0;
-        c.Rstar[q * n + I] = r[q];
+        Rs[q * n + I] = r[q];
     }
     c.alpha[I] = amin;
 }
 
-/* DF-limited prolongation (Eq. prolongation) with injection; a correction that
- * would make rho or p non-positive is skipped. */
-template <int D>
+/* DF-limited prolongation (Eq. prolongation) with injection; the correction
+ * alpha (W - W0) is formed in T.  A correction that would make rho or p
+ * non-positive is skipped. */
+template <int D, class T>
 __global__ void __launch_bounds__(BLOCK) k_prolong(CoarseDev c, double* Wf, const double* af, int nfine,
                                                   int df, unsigned long long* skips) {
     constexpr int NV = D + 2;
@@ -604,10 +710,13 @@ __global__ void __launch_bounds__(BLOCK) k_prolong(CoarseDev c, double* Wf, cons
     if (i >= nfine) return;
     const int I = c.parent[i];
     const int n = c.n;
-    const double a = df ? af[i] : 1.0;
+    const T a = df ? (T)af[i] : (T)1;
     double Wn[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) Wn[q] = Wf[q * nfine + i] + a * (c.W[q * n + I] - c.W0[q * n + I]);
+    for (int q = 0; q < NV; ++q) {
+        const T dl = (T)(c.W[q * n + I] - c.W0[q * n + I]);
+        Wn[q] = Wf[q * nfine + i] + (double)(a * dl);
+    }
     double ke = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) ke += Wn[1 + d] * Wn[1 + d];
@@ -632,22 +741,52 @@ __global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a, double* b
 
 static inline int nblk(long m) { return (int)((m + BLOCK - 1) / BLOCK); }
 
+static inline int blocks(long m, int b) { return (int)((m + b - 1) / b); }
+
+template <int D>
+static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
+    FineDev& f = c->fine;
+    hipStream_t st = c->stream;
+    if (which == 0) {
+        const int b = block ? block : c->blk_recon;
+        k_recon<D><<<blocks(f.n, b), b, 0, st>>>(f, c->kp);
+    } else if (which == 1) {
+        const int b = block ? block : c->blk_flux;
+        k_flux<D><<<blocks((long)f.nf * f.ngp, b), b, 0, st>>>(f, c->kp);
+    } else {
+        /* the norm partials use a fixed 256-thread block */
+        const int b = (mode == FINE_STEP_NORM && !f.pid) ? BLOCK : (block ? block : c->blk_gather);
+        k_gather<D><<<blocks(f.n, b), b, 0, st>>>(f, c->kp, mode, c->ws.partial, c->ws.status);
+    }
+}
+
+void launch_fine_recon(cgks_ctx* c) {
+    if (c->dim == 2) fine_kernel<2>(c, 0, 0, FINE_EVAL);
+    else fine_kernel<3>(c, 0, 0, FINE_EVAL);
+}
+
+void launch_fine_kernel(cgks_ctx* c, int which, int block) {
+    if (c->dim == 2) fine_kernel<2>(c, which, block, FINE_EVAL);
+    else fine_kernel<3>(c, which, block, FINE_EVAL);
+}
+
 template <int D>
 static void fine_residual(cgks_ctx* c, int mode) {
     FineDev& f = c->fine;
     hipStream_t st = c->stream;
-    k_recon<D><<<nblk(f.n), BLOCK, 0, st>>>(f, c->kp);
-    k_flux<D><<<nblk((long)f.nf * f.ngp), BLOCK, 0, st>>>(f, c->kp);
-    k_gather<D><<<nblk(f.n), BLOCK, 0, st>>>(f, c->kp, mode, c->ws.partial, c->ws.status);
-    if (mode == FINE_STEP_NORM)
-        k_norm_finalize<<<1, BLOCK, 0, st>>>(c->ws.partial, nblk(f.n), f.n, c->kp.mach, c->ws.history,
-                                             c->ws.history_cap, c->ws.counter, c->ws.status);
-}
-
-void launch_fine_recon(cgks_ctx* c) {
-    FineDev& f = c->fine;
-    if (c->dim == 2) k_recon<2><<<nblk(f.n), BLOCK, 0, c->stream>>>(f, c->kp);
-    else k_recon<3><<<nblk(f.n), BLOCK, 0, c->stream>>>(f, c->kp);
+    fine_kernel<D>(c, 0, 0, mode);
+    fine_kernel<D>(c, 1, 0, mode);
+    fine_kernel<D>(c, 2, 0, mode);
+    if (mode == FINE_STEP_NORM) {
+        if (f.pid) {
+            k_norm_batch<<<c->ws.nprob, BLOCK, 0, st>>>(f.r2, c->ws.poff, c->ws.ptab, c->ws.history,
+                                                         c->ws.history_cap, c->ws.counter, c->ws.nprob);
+            k_count<<<1, 64, 0, st>>>(c->ws.counter);
+        } else {
+            k_norm_finalize<<<1, BLOCK, 0, st>>>(c->ws.partial, nblk(f.n), f.n, c->kp.mach, c->ws.history,
+                                                 c->ws.history_cap, c->ws.counter, c->ws.status);
+        }
+    }
 }
 
 void launch_fine_residual(cgks_ctx* c, int mode) {
@@ -655,28 +794,41 @@ void launch_fine_residual(cgks_ctx* c, int mode) {
     else fine_residual<3>(c, mode);
 }
 
-void launch_coarse_rhs(cgks_ctx* c, int level, int mode) {
-    CoarseDev& L = c->coarse[level - 1];
-    if (c->dim == 2) k_coarse_rhs<2><<<nblk(L.n), BLOCK, 0, c->stream>>>(L, c->kp, mode);
-    else k_coarse_rhs<3><<<nblk(L.n), BLOCK, 0, c->stream>>>(L, c->kp, mode);
+template <int D, class T>
+static void coarse_rhs(cgks_ctx* c, CoarseDev& L, int mode) {
+    k_coarse_rhs<D, T><<<nblk(L.n), BLOCK, 0, c->stream>>>(L, c->kp, mode);
 }
 
-void launch_lusgs(cgks_ctx* c, int level) {
+void launch_coarse_rhs(cgks_ctx* c, int level, int mode) {
     CoarseDev& L = c->coarse[level - 1];
+    const bool mx = c->p.precision == CGKS_MIXED;
+    if (c->dim == 2) mx ? coarse_rhs<2, float>(c, L, mode) : coarse_rhs<2, double>(c, L, mode);
+    else mx ? coarse_rhs<3, float>(c, L, mode) : coarse_rhs<3, double>(c, L, mode);
+}
+
+template <int D, class T>
+static void lusgs(cgks_ctx* c, CoarseDev& L) {
     for (int pass = 0; pass < 2; ++pass)
         for (int k = 0; k < L.ncolor; ++k) {
             const int col = pass == 0 ? k : L.ncolor - 1 - k;
             const int lo = L.color_off[col], hi = L.color_off[col + 1];
             if (hi <= lo) continue;
-            if (c->dim == 2) k_lusgs<2><<<nblk(hi - lo), BLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
-            else k_lusgs<3><<<nblk(hi - lo), BLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
+            k_lusgs<D, T><<<nblk(hi - lo), BLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
         }
+}
+
+void launch_lusgs(cgks_ctx* c, int level) {
+    CoarseDev& L = c->coarse[level - 1];
+    const bool mx = c->p.precision == CGKS_MIXED;
+    if (c->dim == 2) mx ? lusgs<2, float>(c, L) : lusgs<2, double>(c, L);
+    else mx ? lusgs<3, float>(c, L) : lusgs<3, double>(c, L);
 }
 
 void launch_coarse_update(cgks_ctx* c, int level) {
     CoarseDev& L = c->coarse[level - 1];
     const int m = L.n * c->nv;
-    k_add<<<nblk(m), BLOCK, 0, c->stream>>>(L.W, L.dW, m);
+    if (c->p.precision == CGKS_MIXED) k_add<float><<<nblk(m), BLOCK, 0, c->stream>>>(L.W, L.dW, m);
+    else k_add<double><<<nblk(m), BLOCK, 0, c->stream>>>(L.W, L.dW, m);
 }
 
 void launch_restrict(cgks_ctx* c, int level) {
@@ -689,8 +841,15 @@ void launch_restrict(cgks_ctx* c, int level) {
         CoarseDev& F = c->coarse[level - 1];
         Wf = F.W; Vf = F.V; rf = F.rhs; af = F.alpha; nfine = F.n;
     }
-    if (c->dim == 2) k_restrict<2><<<nblk(G.n), BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
-    else k_restrict<3><<<nblk(G.n), BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+    const bool mx = c->p.precision == CGKS_MIXED;
+    const int nb = nblk(G.n);
+    if (c->dim == 2) {
+        if (mx) k_restrict<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        else k_restrict<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+    } else {
+        if (mx) k_restrict<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        else k_restrict<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+    }
 }
 
 void launch_prolong(cgks_ctx* c, int level) {
@@ -704,10 +863,16 @@ void launch_prolong(cgks_ctx* c, int level) {
         CoarseDev& F = c->coarse[level - 1];
         Wf = F.W; af = F.alpha; nfine = F.n;
     }
-    if (c->dim == 2)
-        k_prolong<2><<<nblk(nfine), BLOCK, 0, c->stream>>>(G, Wf, af, nfine, c->kp.df_prolong, c->ws.skips);
-    else
-        k_prolong<3><<<nblk(nfine), BLOCK, 0, c->stream>>>(G, Wf, af, nfine, c->kp.df_prolong, c->ws.skips);
+    const bool mx = c->p.precision == CGKS_MIXED;
+    const int nb = nblk(nfine), df = c->kp.df_prolong;
+    unsigned long long* sk = c->ws.skips;
+    if (c->dim == 2) {
+        if (mx) k_prolong<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+        else k_prolong<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+    } else {
+        if (mx) k_prolong<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+        else k_prolong<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+    }
 }
 
 void launch_save_state(cgks_ctx* c) {

@@ -184,3 +184,45 @@ def test_graph_replay_is_bitwise_reproducible(cg):
     h1 = np.array([g.vcycle() for _ in range(6)])
     W1, _, _ = g.get_state()
     assert np.array_equal(h1, runs[0][0]) and np.array_equal(W1, runs[0][1])
+
+
+def test_long_trajectory_parity_viscous_steady(cg, orc):
+    """25 V-cycles of a steady viscous case (Mach 0.15, Re 40, isothermal wall)
+    from free stream: per-cycle norms and the final state track the oracle.  A
+    longer horizon than the 10-cycle tests, so that a kernel defect that only
+    shows after many cycles cannot hide."""
+    mesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=2, wall_tag=sm.ISOTHERMAL)
+    g, o = _pair(cg, orc, mesh, mach=0.15, reynolds=40.0)
+    g.init_freestream()
+    o.init_freestream()
+    ng = g.run_cycles(25)
+    no = np.array([o.vcycle() for _ in range(25)])
+    np.testing.assert_allclose(ng, no, rtol=1e-9)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-9 * np.abs(Wo).max()
+
+
+def test_batch_equals_individual_solves(cg):
+    """A batch advances each problem exactly as its own context would: fine states
+    bitwise equal after 5 cycles (same kernels, per-problem parameters), norms
+    equal to rounding (the batch reduces per problem in another fixed order)."""
+    specs = [(sm.annulus(12, 4, jitter=0.1, seed=1, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=2.0, reynolds=500.0)),
+             (sm.annulus(16, 4, jitter=0.2, seed=2, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=0.5, reynolds=2000.0)),
+             (sm.annulus(8, 3, jitter=0.1, seed=3, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=4.0, reynolds=1e4,
+                                                                                       wall_T_ratio=2.0))]
+    singles, members = [], []
+    for mesh, p in specs:
+        for lst in (singles, members):
+            s = cg.Solver(mesh, n_levels=3, **p)
+            s.init_freestream()
+            lst.append(s)
+    ref = [s.run_cycles(5) for s in singles]
+    batch = cg.Batch(members)
+    hist = batch.run_cycles(5)
+    batch.sync_states()
+    for b in range(len(specs)):
+        np.testing.assert_allclose(hist[b], ref[b], rtol=1e-12)
+        Wb, gb, ab = members[b].get_state()
+        Ws, gs, as_ = singles[b].get_state()
+        assert np.array_equal(Wb, Ws) and np.array_equal(gb, gs) and np.array_equal(ab, as_)
