@@ -243,6 +243,48 @@ int cgks_batch_solve(cgks_batch* b, double tol, int max_cycles, int* cycles_out,
 int cgks_batch_get_state(cgks_batch* b);
 void cgks_batch_destroy(cgks_batch* b);
 
+/* Warm-start surrogate.  The paper starts every steady solve from the free
+ * stream (Sec. 6); this optional initial state comes instead from a
+ * 5 -> 256 -> 256 -> 256 -> 4 multilayer perceptron with SiLU activations,
+ * trained by Adam on the mean squared error.  Every matrix product runs on the
+ * BF16 matrix cores with FP32 accumulation; master weights, biases and Adam
+ * moments are FP32.  Inputs per sample: 5 standardised features (Mach,
+ * log10 Re, x, y, wall distance); outputs: 4 standardised targets
+ * (log rho/rho_inf, u/U_inf, v/U_inf, log p/p_inf), where U_inf is the free-stream speed
+ * (the Mach number in the solver's units).  X, Y are device pointers, row
+ * major [n][5] and [n][4] float.  Calls are stream-ordered on the stream set
+ * with cgks_mlp_set_stream (NULL = the null stream) and synchronise before
+ * returning.  Errors: CGKS_EINVAL (null pointer, n <= 0, lr <= 0),
+ * CGKS_EDEVICE (allocation or launch failure). */
+typedef struct cgks_mlp cgks_mlp;
+/* Create with He-uniform weights drawn from a 64-bit Mersenne twister seeded
+ * with `seed`, zero biases and zero Adam moments. */
+int cgks_mlp_create(cgks_mlp** out, int seed);
+void cgks_mlp_destroy(cgks_mlp* m);
+int cgks_mlp_set_stream(cgks_mlp* m, void* stream);
+/* Number of parameters; the flat host layout is, per layer, W [out][in]
+ * (row major) followed by b [out]. */
+int cgks_mlp_num_params(void);
+int cgks_mlp_get_weights(cgks_mlp* m, float* flat);
+/* Sets the weights and resets the Adam state (step count and moments). */
+int cgks_mlp_set_weights(cgks_mlp* m, const float* flat);
+/* Y = network(X). */
+int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n);
+/* Loss mean_n sum_k (out - Y)^2 (host float) and, if grads_out is not NULL,
+ * its gradient in the flat host layout; the weights are not changed. */
+int cgks_mlp_grads(cgks_mlp* m, const float* X, const float* Y, int n, float* grads_out, float* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * batch; loss (host, may be NULL) is the loss before the step. */
+int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, float lr, float* loss);
+/* Fine-level initial state of a 2-D context from the network.  fmean/fstd
+ * standardise the features, tmean/tstd de-standardise the targets (host
+ * float[5] and float[4]).  Wall distance is taken to the nearest wall-face
+ * centre.  Cells whose prediction is non-finite or non-physical take the free
+ * stream; n_fallback (may be NULL) receives their count.  Gradients are
+ * zeroed and alpha set to 1, as cgks_set_state does. */
+int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, const float* fstd, const float* tmean,
+                       const float* tstd, int* n_fallback);
+
 /* Counters: positivity-guard hits of the reconstruction, prolongation skips. */
 int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);
 

@@ -21,6 +21,7 @@ SOURCES = [
     ("setup.cpp", ["-ffp-contract=off"]),    # host set-up: fixed expression order
     ("api.cpp", []),
     ("kernels.hip", []),
+    ("mlp.hip", []),
 ]
 
 

@@ -86,6 +86,16 @@ _sigs = {
     "cgks_batch_solve": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "cgks_batch_get_state": (C.c_int, [_P]),
     "cgks_batch_destroy": (None, [_P]),
+    "cgks_mlp_create": (C.c_int, [C.POINTER(_P), C.c_int]),
+    "cgks_mlp_destroy": (None, [_P]),
+    "cgks_mlp_set_stream": (C.c_int, [_P, _P]),
+    "cgks_mlp_num_params": (C.c_int, []),
+    "cgks_mlp_get_weights": (C.c_int, [_P, _P]),
+    "cgks_mlp_set_weights": (C.c_int, [_P, _P]),
+    "cgks_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int]),
+    "cgks_mlp_grads": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
+    "cgks_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
+    "cgks_init_from_mlp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.POINTER(C.c_int)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -339,6 +349,97 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             _lib.cgks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _f32(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+class MLP:
+    """Warm-start surrogate (see cgks_mlp_* in include/cgks.h).  X and Y are
+    float32 device tensors of shape [n, 5] and [n, 4]."""
+
+    SIZES = (5, 256, 256, 256, 4)
+
+    def __init__(self, seed=0, stream=None):
+        h = _P()
+        rc = _lib.cgks_mlp_create(C.byref(h), seed)
+        if rc != OK:
+            raise CgksError(rc, "cgks_mlp_create")
+        self.h = h
+        if stream is not None:
+            self._check(_lib.cgks_mlp_set_stream(self.h, _P(stream)))
+
+    @staticmethod
+    def num_params():
+        return _lib.cgks_mlp_num_params()
+
+    def _check(self, rc, what="mlp"):
+        if rc != OK:
+            raise CgksError(rc, what)
+
+    @staticmethod
+    def _dev(t, cols):
+        if not (hasattr(t, "is_cuda") and t.is_cuda) or str(t.dtype) != "torch.float32" or not t.is_contiguous():
+            raise TypeError("expected a contiguous float32 device tensor")
+        if t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"expected shape [n, {cols}]")
+        return t.data_ptr(), t.shape[0]
+
+    def get_weights(self):
+        w = np.zeros(self.num_params(), dtype=np.float32)
+        self._check(_lib.cgks_mlp_get_weights(self.h, w.ctypes.data))
+        return w
+
+    def set_weights(self, flat):
+        w = _f32(flat, self.num_params())
+        self._check(_lib.cgks_mlp_set_weights(self.h, w.ctypes.data))
+
+    def forward(self, X, Y):
+        px, n = self._dev(X, 5)
+        py, ny = self._dev(Y, 4)
+        if ny != n:
+            raise ValueError("X and Y differ in rows")
+        self._check(_lib.cgks_mlp_forward(self.h, px, py, n), "cgks_mlp_forward")
+
+    def grads(self, X, Y):
+        px, n = self._dev(X, 5)
+        py, _ = self._dev(Y, 4)
+        g = np.zeros(self.num_params(), dtype=np.float32)
+        loss = C.c_float()
+        self._check(_lib.cgks_mlp_grads(self.h, px, py, n, g.ctypes.data, C.byref(loss)), "cgks_mlp_grads")
+        return float(loss.value), g
+
+    def train_step(self, X, Y, lr):
+        px, n = self._dev(X, 5)
+        py, _ = self._dev(Y, 4)
+        loss = C.c_float()
+        self._check(_lib.cgks_mlp_train_step(self.h, px, py, n, C.c_float(lr), C.byref(loss)), "cgks_mlp_train_step")
+        return float(loss.value)
+
+    def init_solver(self, solver, fmean, fstd, tmean, tstd):
+        """Warm-start a 2-D solver's fine state; returns the number of fallback cells."""
+        fm, fs, tm, ts = _f32(fmean, 5), _f32(fstd, 5), _f32(tmean, 4), _f32(tstd, 4)
+        nfb = C.c_int()
+        rc = _lib.cgks_init_from_mlp(solver.ctx, self.h, fm.ctypes.data, fs.ctypes.data, tm.ctypes.data,
+                                     ts.ctypes.data, C.byref(nfb))
+        if rc != OK:
+            raise CgksError(rc, _lib.cgks_last_error(solver.ctx).decode())
+        return int(nfb.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.cgks_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

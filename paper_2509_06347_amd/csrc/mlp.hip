@@ -1,0 +1,553 @@
+/*
+ * Warm-start surrogate: a 5 -> 256 -> 256 -> 256 -> 4 MLP with SiLU, trained
+ * and evaluated with BF16 matrix-core (MFMA) GEMMs and FP32 accumulation.
+ *
+ * Master weights, biases and Adam moments are FP32; every GEMM reads BF16
+ * copies of weights and activations.  Weights follow y = x W^T + b with W
+ * stored [out][in] (in padded to a multiple of 32).  The inputs are the
+ * standardised features (Mach, log10 Re, x, y, wall distance); the outputs the
+ * standardised targets (log rho, u/U_inf, v/U_inf, log p).
+ *
+ * GEMM: C[M x N] = A[M x K] B[K x N] with arbitrary strides, one 64 x 64 block
+ * tile per 256-thread block (four wave64s, each 32 x 32 = 2 x 2 MFMA tiles of
+ * v_mfma_f32_16x16x32_bf16), K staged through LDS in steps of 32.
+ * Fragment layout of the 16x16x32 BF16 MFMA: lane l holds A row (l % 16) and
+ * B column (l % 16), each with the 8 consecutive K values 8 * (l / 16) ..;
+ * the accumulator holds column (l % 16), rows 4 * (l / 16) .. + 3.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "cgks_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int NL = 4;                                  /* layers */
+constexpr int DIN[NL] = {5, 256, 256, 256};
+constexpr int DOUT[NL] = {256, 256, 256, 4};
+constexpr int KPAD[NL] = {32, 256, 256, 256};          /* padded input width */
+constexpr int NPAD[NL] = {256, 256, 256, 16};          /* padded output width */
+
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu_f(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+/*
+ * C = A B (+ epilogue).  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
+ * EPI_BIAS_SILU: Z = C + bias[n] -> Cz (fp32) and Cb = bf16(silu(Z)).
+ * EPI_BIAS:      C + bias[n] -> C (fp32).
+ * EPI_DSILU:     Cb = bf16(C * silu'(Zin[m, n]))  (backward through SiLU).
+ * EPI_STORE:     C -> C (fp32).
+ * Block z of the grid's third dimension sums k in [z kc, min(K, (z + 1) kc))
+ * and, for EPI_STORE, writes to Cz + z zstride (split-K partials).
+ * Out-of-range A/B elements read as zero; only in-range C elements are stored.
+ */
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const __bf16* __restrict__ A, long sam, long sak,
+                                              const __bf16* __restrict__ B, long sbk, long sbn, float* Cz, long ldc,
+                                              __bf16* Cb, long ldb, const float* bias, const float* Zin, long ldz,
+                                              int kc, long zstride) {
+    __shared__ __bf16 As[64][40];   /* [m][k], padded rows */
+    __shared__ __bf16 Bs[64][40];   /* [n][k] */
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lr = t >> 2, lk = (t & 3) * 8;   /* loader: row/col lr, k chunk lk..lk+7 */
+    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+    if (EPI == EPI_STORE) Cz += blockIdx.z * zstride;
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int m = m0 + lr, k = k0 + lk + e, n = n0 + lr;
+            As[lr][lk + e] = (m < M && k < ke) ? A[(long)m * sam + (long)k * sak] : (__bf16)0.0f;
+            Bs[lr][lk + e] = (n < N && k < ke) ? B[(long)k * sbk + (long)n * sbn] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = As[wm + 16 * i + fr][fk + e];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                bf16x8 b;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[e] = Bs[wn + 16 * j + fr][fk + e];
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    const int cc = lane & 15, cr = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + cr + r, n = n0 + wn + 16 * j + cc;
+                if (m >= M || n >= N) continue;
+                float v = acc[i][j][r];
+                if (EPI == EPI_BIAS_SILU) {
+                    v += bias[n];
+                    Cz[(long)m * ldc + n] = v;
+                    Cb[(long)m * ldb + n] = (__bf16)silu_f(v);
+                } else if (EPI == EPI_BIAS) {
+                    Cz[(long)m * ldc + n] = v + bias[n];
+                } else if (EPI == EPI_DSILU) {
+                    Cb[(long)m * ldb + n] = (__bf16)(v * dsilu_f(Zin[(long)m * ldz + n]));
+                } else {
+                    Cz[(long)m * ldc + n] = v;
+                }
+            }
+}
+
+/* C[i] = sum_z P[z][i] in increasing z (fixed order). */
+__global__ void k_splitk_reduce(const float* P, int nz, long cnt, float* C) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    float v = 0.0f;
+    for (int z = 0; z < nz; ++z) v += P[z * cnt + i];
+    C[i] = v;
+}
+
+/* Features [n][5] (fp32) -> bf16 [n][32] zero-padded. */
+__global__ void k_pack_input(const float* X, __bf16* H, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 32) return;
+    const int i = t >> 5, k = t & 31;
+    H[t] = (k < 5) ? (__bf16)X[i * 5 + k] : (__bf16)0.0f;
+}
+
+/* Output gradient 2 (out - Y) / n as bf16 [n][16] zero-padded, and per-sample squared error. */
+__global__ void k_out_grad(const float* out, const float* Y, __bf16* G, float* se, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int k = 0; k < 16; ++k) {
+        float g = 0.0f;
+        if (k < 4) {
+            const float d = out[i * 16 + k] - Y[i * 4 + k];
+            s += d * d;
+            g = 2.0f * d / (float)n;
+        }
+        G[i * 16 + k] = (__bf16)g;
+    }
+    se[i] = s;
+}
+
+/* Column sums of a [n][ncol] bf16 matrix in a fixed order (bias gradients). */
+__global__ void k_colsum(const __bf16* G, int n, int ncol, float* out) {
+    const int c = blockIdx.x;
+    __shared__ float sh[256];
+    float v = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) v += (float)G[(long)i * ncol + c];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+__global__ void k_sum(const float* a, int n, float* out) {
+    __shared__ float sh[256];
+    float v = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) v += a[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0] / (float)n;
+}
+
+/* Adam on fp32 master parameters; refreshes the bf16 weight copy (bias: wb null). */
+__global__ void k_adam(float* p, const float* g, float* m, float* v, __bf16* wb, int cnt, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const float gi = g[t];
+    const float mi = b1 * m[t] + (1.0f - b1) * gi;
+    const float vi = b2 * v[t] + (1.0f - b2) * gi * gi;
+    m[t] = mi;
+    v[t] = vi;
+    const float pn = p[t] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[t] = pn;
+    if (wb) wb[t] = (__bf16)pn;
+}
+
+__global__ void k_to_bf16(const float* a, __bf16* b, int cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt) b[t] = (__bf16)a[t];
+}
+
+/* Network output -> conservative state [n][D+2] (AoS), with a free-stream fallback per cell. */
+template <int D>
+__global__ void k_mlp_state(const float* out, const float* tt, double mach, double gamma, const double* uinf, double* W,
+                            int n, int* fallback) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y[4];
+    for (int k = 0; k < 4; ++k) y[k] = (double)out[i * 16 + k] * (double)tt[4 + k] + (double)tt[k];
+    const double rho = exp(y[0]), u = y[1] * mach, v = y[2] * mach, p = exp(y[3]) / gamma;
+    const bool ok = isfinite(rho) && isfinite(u) && isfinite(v) && isfinite(p) && rho > 1e-6 && p > 1e-8 &&
+                    rho < 1e4 && p < 1e6;
+    double r = rho, U[3] = {u, v, 0.0}, pr = p;
+    if (!ok) {
+        atomicAdd(fallback, 1);
+        r = 1.0;
+        pr = 1.0 / gamma;
+        for (int d = 0; d < 3; ++d) U[d] = uinf[d];
+    }
+    double ke = 0.0;
+    double* w = W + (long)i * (D + 2);
+    w[0] = r;
+    for (int d = 0; d < D; ++d) {
+        w[1 + d] = r * U[d];
+        ke += U[d] * U[d];
+    }
+    w[D + 1] = pr / (gamma - 1.0) + 0.5 * r * ke;
+}
+
+inline int nb(long m, int b) { return (int)((m + b - 1) / b); }
+
+}  // namespace
+
+struct cgks_mlp {
+    float* P[NL][2];            /* master W [NPAD?] -> stored [DOUT][KPAD], bias [DOUT] */
+    float *Mo[NL][2], *Vo[NL][2], *Gr[NL][2];
+    __bf16* Wb[NL];             /* bf16 copy of W, [DOUT][KPAD] */
+    int t = 0;
+    int cap = 0;                /* samples the workspace holds */
+    __bf16* H[NL];              /* layer inputs (bf16), [cap][KPAD] */
+    float* Z[NL];               /* pre-activations (fp32), [cap][NPAD] */
+    float* out;                 /* [cap][16] */
+    __bf16* G[NL + 1];          /* gradients w.r.t. layer outputs, bf16 */
+    float* se;                  /* per-sample squared error */
+    float* dloss;
+    float* part;                /* split-K partials, SPLITK * 256 * 256 */
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    std::string err;
+};
+
+namespace {
+
+template <class T>
+hipError_t mal(cgks_mlp* m, T** p, size_t cnt) {
+    hipError_t e = hipMalloc((void**)p, (cnt ? cnt : 1) * sizeof(T));
+    if (e == hipSuccess) m->allocs.push_back((void*)*p);
+    return e;
+}
+
+size_t wcount(int l) { return (size_t)DOUT[l] * KPAD[l]; }
+
+int ensure_ws(cgks_mlp* m, int n) {
+    if (n <= m->cap) return CGKS_OK;
+    int cap = std::max(n, 2 * m->cap);
+    bool ok = true;
+    for (int l = 0; l < NL; ++l) {
+        ok &= mal(m, &m->H[l], (size_t)cap * KPAD[l]) == hipSuccess;
+        ok &= mal(m, &m->Z[l], (size_t)cap * NPAD[l]) == hipSuccess;
+    }
+    ok &= mal(m, &m->out, (size_t)cap * 16) == hipSuccess;
+    for (int l = 0; l <= NL; ++l) ok &= mal(m, &m->G[l], (size_t)cap * (l < NL ? KPAD[l] : 16)) == hipSuccess;
+    ok &= mal(m, &m->se, (size_t)cap) == hipSuccess;
+    if (!ok) return CGKS_EDEVICE;
+    m->cap = cap;
+    return CGKS_OK;
+}
+
+template <int EPI>
+void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B, long sbk, long sbn,
+          float* Cz, long ldc, __bf16* Cb, long ldb, const float* bias, const float* Zin, long ldz) {
+    dim3 grid(nb(N, 64), nb(M, 64), 1);
+    k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, K, 0);
+}
+
+/* C[M][N] (ldc == N) = A B with the K range split over up to SPLITK blocks;
+ * the partials are summed in a fixed order, so the result is reproducible. */
+constexpr int SPLITK = 64;
+void gemm_splitk(cgks_mlp* m, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B, long sbk,
+                 long sbn, float* C);
+
+void gemm_splitk(cgks_mlp* m, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B, long sbk,
+                 long sbn, float* C) {
+    const int nz = std::max(1, std::min(SPLITK, K / 1024));
+    const int kc = ((K + nz - 1) / nz + 31) / 32 * 32;
+    const int z = (K + kc - 1) / kc;
+    dim3 grid(nb(N, 64), nb(M, 64), z);
+    const long cnt = (long)M * N;
+    k_gemm<EPI_STORE><<<grid, 256, 0, m->stream>>>(M, N, K, A, sam, sak, B, sbk, sbn, m->part, N, nullptr, 0, nullptr,
+                                                    nullptr, 0, kc, cnt);
+    k_splitk_reduce<<<nb(cnt, 256), 256, 0, m->stream>>>(m->part, z, cnt, C);
+}
+
+/* forward of n samples (X device fp32 [n][5]) into m->out [n][16] */
+void forward(cgks_mlp* m, const float* X, int n) {
+    hipStream_t st = m->stream;
+    k_pack_input<<<nb((long)n * 32, 256), 256, 0, st>>>(X, m->H[0], n);
+    for (int l = 0; l < NL; ++l) {
+        /* Z = H W^T + b : A = H [n][KPAD], B(k, o) = W[o][k] */
+        if (l < NL - 1)
+            gemm<EPI_BIAS_SILU>(st, n, DOUT[l], KPAD[l], m->H[l], KPAD[l], 1, m->Wb[l], 1, KPAD[l], m->Z[l], NPAD[l],
+                                m->H[l + 1], KPAD[l + 1], m->P[l][1], nullptr, 0);
+        else
+            gemm<EPI_BIAS>(st, n, DOUT[l], KPAD[l], m->H[l], KPAD[l], 1, m->Wb[l], 1, KPAD[l], m->out, 16, nullptr, 0,
+                           m->P[l][1], nullptr, 0);
+    }
+}
+
+/* gradients of the mean squared error into m->Gr, loss into m->dloss */
+void backward(cgks_mlp* m, const float* Y, int n) {
+    hipStream_t st = m->stream;
+    k_out_grad<<<nb(n, 256), 256, 0, st>>>(m->out, Y, m->G[NL], m->se, n);
+    k_sum<<<1, 256, 0, st>>>(m->se, n, m->dloss);
+    for (int l = NL - 1; l >= 0; --l) {
+        const int ldg = (l == NL - 1) ? 16 : KPAD[l + 1];  /* row stride of the output gradient */
+        /* dW[o][k] = sum_i G[i][o] H[i][k] : A(o, i) = G[i][o], B(i, k) = H[i][k] */
+        gemm_splitk(m, DOUT[l], KPAD[l], n, m->G[l + 1], 1, ldg, m->H[l], KPAD[l], 1, m->Gr[l][0]);
+        k_colsum<<<DOUT[l], 256, 0, st>>>(m->G[l + 1], n, ldg, m->Gr[l][1]);
+        if (l > 0) {
+            /* G_l[i][k] = (sum_o G[i][o] W[o][k]) * silu'(Z_{l-1}[i][k]) */
+            gemm<EPI_DSILU>(st, n, DIN[l], DOUT[l], m->G[l + 1], ldg, 1, m->Wb[l], KPAD[l], 1, nullptr, 0, m->G[l],
+                            KPAD[l], nullptr, m->Z[l - 1], NPAD[l - 1]);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int cgks_mlp_create(cgks_mlp** out, int seed) {
+    if (!out) return CGKS_EINVAL;
+    cgks_mlp* m = new cgks_mlp();
+    std::mt19937_64 rng((uint64_t)seed);
+    bool ok = mal(m, &m->dloss, 1) == hipSuccess && mal(m, &m->part, (size_t)SPLITK * 256 * 256) == hipSuccess;
+    for (int l = 0; l < NL && ok; ++l) {
+        const size_t nw = wcount(l), nbias = DOUT[l];
+        std::vector<float> W(nw, 0.0f), b(nbias, 0.0f);
+        const double bound = std::sqrt(6.0 / DIN[l]);
+        std::uniform_real_distribution<double> U(-bound, bound);
+        for (int o = 0; o < DOUT[l]; ++o)
+            for (int k = 0; k < DIN[l]; ++k) W[(size_t)o * KPAD[l] + k] = (float)U(rng);
+        for (int j = 0; j < 2 && ok; ++j) {
+            const size_t cnt = j ? nbias : nw;
+            ok &= mal(m, &m->P[l][j], cnt) == hipSuccess && mal(m, &m->Mo[l][j], cnt) == hipSuccess &&
+                  mal(m, &m->Vo[l][j], cnt) == hipSuccess && mal(m, &m->Gr[l][j], cnt) == hipSuccess;
+            if (!ok) break;
+            ok &= hipMemcpy(m->P[l][j], j ? b.data() : W.data(), cnt * 4, hipMemcpyHostToDevice) == hipSuccess;
+            ok &= hipMemset(m->Mo[l][j], 0, cnt * 4) == hipSuccess && hipMemset(m->Vo[l][j], 0, cnt * 4) == hipSuccess;
+        }
+        ok &= mal(m, &m->Wb[l], nw) == hipSuccess;
+        if (ok) k_to_bf16<<<nb(nw, 256), 256>>>(m->P[l][0], m->Wb[l], (int)nw);
+    }
+    if (!ok || hipDeviceSynchronize() != hipSuccess) {
+        cgks_mlp_destroy(m);
+        return CGKS_EDEVICE;
+    }
+    *out = m;
+    return CGKS_OK;
+}
+
+void cgks_mlp_destroy(cgks_mlp* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+}
+
+int cgks_mlp_set_stream(cgks_mlp* m, void* stream) {
+    if (!m) return CGKS_EINVAL;
+    m->stream = (hipStream_t)stream;
+    return CGKS_OK;
+}
+
+int cgks_mlp_num_params(void) {
+    int s = 0;
+    for (int l = 0; l < NL; ++l) s += DOUT[l] * DIN[l] + DOUT[l];
+    return s;
+}
+
+/* Flat host layout: for each layer W [out][in] (unpadded) then b [out]. */
+int cgks_mlp_get_weights(cgks_mlp* m, float* flat) {
+    if (!m || !flat) return CGKS_EINVAL;
+    size_t o = 0;
+    for (int l = 0; l < NL; ++l) {
+        std::vector<float> W(wcount(l));
+        if (hipMemcpy(W.data(), m->P[l][0], W.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return CGKS_EDEVICE;
+        for (int r = 0; r < DOUT[l]; ++r)
+            for (int k = 0; k < DIN[l]; ++k) flat[o++] = W[(size_t)r * KPAD[l] + k];
+        if (hipMemcpy(flat + o, m->P[l][1], DOUT[l] * 4, hipMemcpyDeviceToHost) != hipSuccess) return CGKS_EDEVICE;
+        o += DOUT[l];
+    }
+    return CGKS_OK;
+}
+
+int cgks_mlp_set_weights(cgks_mlp* m, const float* flat) {
+    if (!m || !flat) return CGKS_EINVAL;
+    size_t o = 0;
+    for (int l = 0; l < NL; ++l) {
+        std::vector<float> W(wcount(l), 0.0f);
+        for (int r = 0; r < DOUT[l]; ++r)
+            for (int k = 0; k < DIN[l]; ++k) W[(size_t)r * KPAD[l] + k] = flat[o++];
+        if (hipMemcpy(m->P[l][0], W.data(), W.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return CGKS_EDEVICE;
+        if (hipMemcpy(m->P[l][1], flat + o, DOUT[l] * 4, hipMemcpyHostToDevice) != hipSuccess) return CGKS_EDEVICE;
+        o += DOUT[l];
+        k_to_bf16<<<nb(wcount(l), 256), 256, 0, m->stream>>>(m->P[l][0], m->Wb[l], (int)wcount(l));
+        (void)hipMemset(m->Mo[l][0], 0, wcount(l) * 4);
+        (void)hipMemset(m->Vo[l][0], 0, wcount(l) * 4);
+        (void)hipMemset(m->Mo[l][1], 0, DOUT[l] * 4);
+        (void)hipMemset(m->Vo[l][1], 0, DOUT[l] * 4);
+    }
+    m->t = 0;
+    return hipStreamSynchronize(m->stream) == hipSuccess ? CGKS_OK : CGKS_EDEVICE;
+}
+
+int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n) {
+    if (!m || !X || !Y || n <= 0) return CGKS_EINVAL;
+    int rc = ensure_ws(m, n);
+    if (rc) return rc;
+    forward(m, X, n);
+    if (hipMemcpy2DAsync(Y, 4 * sizeof(float), m->out, 16 * sizeof(float), 4 * sizeof(float), n,
+                         hipMemcpyDeviceToDevice, m->stream) != hipSuccess)
+        return CGKS_EDEVICE;
+    return hipStreamSynchronize(m->stream) == hipSuccess ? CGKS_OK : CGKS_EDEVICE;
+}
+
+int cgks_mlp_grads(cgks_mlp* m, const float* X, const float* Y, int n, float* grads_out, float* loss) {
+    if (!m || !X || !Y || n <= 0) return CGKS_EINVAL;
+    int rc = ensure_ws(m, n);
+    if (rc) return rc;
+    forward(m, X, n);
+    backward(m, Y, n);
+    if (hipStreamSynchronize(m->stream) != hipSuccess) return CGKS_EDEVICE;
+    if (loss && hipMemcpy(loss, m->dloss, 4, hipMemcpyDeviceToHost) != hipSuccess) return CGKS_EDEVICE;
+    if (grads_out) {
+        size_t o = 0;
+        for (int l = 0; l < NL; ++l) {
+            std::vector<float> G(wcount(l));
+            if (hipMemcpy(G.data(), m->Gr[l][0], G.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return CGKS_EDEVICE;
+            for (int r = 0; r < DOUT[l]; ++r)
+                for (int k = 0; k < DIN[l]; ++k) grads_out[o++] = G[(size_t)r * KPAD[l] + k];
+            if (hipMemcpy(grads_out + o, m->Gr[l][1], DOUT[l] * 4, hipMemcpyDeviceToHost) != hipSuccess)
+                return CGKS_EDEVICE;
+            o += DOUT[l];
+        }
+    }
+    return CGKS_OK;
+}
+
+int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, float lr, float* loss) {
+    if (!m || !X || !Y || n <= 0 || !(lr > 0.0f)) return CGKS_EINVAL;
+    int rc = ensure_ws(m, n);
+    if (rc) return rc;
+    forward(m, X, n);
+    backward(m, Y, n);
+    m->t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)m->t), c2 = 1.0f - std::pow(b2, (float)m->t);
+    for (int l = 0; l < NL; ++l)
+        for (int j = 0; j < 2; ++j) {
+            const int cnt = j ? DOUT[l] : (int)wcount(l);
+            k_adam<<<nb(cnt, 256), 256, 0, m->stream>>>(m->P[l][j], m->Gr[l][j], m->Mo[l][j], m->Vo[l][j],
+                                                        j ? nullptr : m->Wb[l], cnt, lr, b1, b2, 1e-8f, c1, c2);
+        }
+    if (loss) {
+        if (hipMemcpyAsync(loss, m->dloss, 4, hipMemcpyDeviceToHost, m->stream) != hipSuccess) return CGKS_EDEVICE;
+    }
+    return hipStreamSynchronize(m->stream) == hipSuccess ? CGKS_OK : CGKS_EDEVICE;
+}
+
+}  // extern "C"
+
+/* Initial state from the network: features per fine cell (Mach, log10 Re,
+ * x, y, distance to the nearest wall-face centre), standardised with fmean /
+ * fstd; outputs de-standardised with tmean / tstd; cells whose prediction is
+ * non-physical or non-finite fall back to the free stream. */
+extern "C" int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, const float* fstd,
+                                  const float* tmean, const float* tstd, int* n_fallback) {
+    using namespace cgks;
+    if (!c || !m || !fmean || !fstd || !tmean || !tstd) return CGKS_EINVAL;
+    if (!c->have_mesh) return fail(c, CGKS_EINVAL, "no mesh");
+    if (c->dim != 2) return fail(c, CGKS_EINVAL, "the warm start is defined for 2-D meshes");
+    for (int k = 0; k < 5; ++k)
+        if (!(fstd[k] > 0.0f)) return fail(c, CGKS_EINVAL, "feature scales must be positive");
+    const HLevel& H = c->hl[0];
+    const int n = H.n;
+    std::vector<double> wx, wy;
+    for (const HFace& f : H.faces)
+        if (f.R < 0 && (f.tag == CGKS_TAG_SLIP || f.tag == CGKS_TAG_ISOTHERMAL || f.tag == CGKS_TAG_ADIABATIC)) {
+            wx.push_back(f.xc[0]);
+            wy.push_back(f.xc[1]);
+        }
+    const double lre = c->p.reynolds > 0.0 ? std::log10(c->p.reynolds) : 0.0;
+    std::vector<float> X((size_t)n * 5);
+    for (int i = 0; i < n; ++i) {
+        const double x = H.C[2 * i], y = H.C[2 * i + 1];
+        double dmin = wx.empty() ? 0.0 : 1e300;
+        for (size_t k = 0; k < wx.size(); ++k)
+            dmin = std::min(dmin, (x - wx[k]) * (x - wx[k]) + (y - wy[k]) * (y - wy[k]));
+        const double feat[5] = {c->p.mach, lre, x, y, std::sqrt(dmin)};
+        for (int k = 0; k < 5; ++k) X[(size_t)i * 5 + k] = (float)((feat[k] - fmean[k]) / fstd[k]);
+    }
+    float tt[8];
+    for (int k = 0; k < 4; ++k) {
+        tt[k] = tmean[k];
+        tt[4 + k] = tstd[k];
+    }
+    float *dX = nullptr, *dt = nullptr;
+    double *du = nullptr, *dW = nullptr;
+    int* dfb = nullptr;
+    int rc = CGKS_OK;
+    if (hipMalloc((void**)&dX, X.size() * 4) != hipSuccess || hipMalloc((void**)&dt, 8 * 4) != hipSuccess ||
+        hipMalloc((void**)&du, 3 * 8) != hipSuccess || hipMalloc((void**)&dW, (size_t)n * 4 * 8) != hipSuccess ||
+        hipMalloc((void**)&dfb, 4) != hipSuccess)
+        rc = fail(c, CGKS_EDEVICE, "device allocation failed");
+    if (rc == CGKS_OK) rc = ensure_ws(m, n);
+    int fb = 0;
+    if (rc == CGKS_OK) {
+        bool ok = hipMemcpy(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(dt, tt, 8 * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(du, c->kp.u_inf, 3 * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemset(dfb, 0, 4) == hipSuccess;
+        if (ok) {
+            hipStream_t keep = m->stream;
+            m->stream = c->stream;
+            forward(m, dX, n);
+            k_mlp_state<2><<<nb(n, 256), 256, 0, c->stream>>>(m->out, dt, c->p.mach, c->p.gamma, du, dW, n, dfb);
+            m->stream = keep;
+            ok = hipMemcpyAsync(&fb, dfb, 4, hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+                 hipStreamSynchronize(c->stream) == hipSuccess;
+        }
+        rc = ok ? cgks_set_state(c, dW, nullptr, nullptr, CGKS_DEVICE) : fail(c, CGKS_EDEVICE, "warm start failed");
+    }
+    if (n_fallback) *n_fallback = fb;
+    (void)hipFree(dX);
+    (void)hipFree(dt);
+    (void)hipFree(du);
+    (void)hipFree(dW);
+    (void)hipFree(dfb);
+    return rc;
+}

@@ -152,7 +152,9 @@ def test_vcycle_trajectory_parity(cg, orc, case):
     tol = 1e-8 if "reynolds" in params else 1e-10
     assert np.abs(Wg - Wo).max() <= tol * np.abs(Wo).max()
     assert np.abs(gg - go).max() <= 10 * tol * max(np.abs(go).max(), 1e-12)
-    np.testing.assert_allclose(ag, ao, rtol=10 * tol, atol=1e-12)
+    # alpha = 1 / (1 + D^2) lies in (0, 1] and D sums jumps normalised by local
+    # values, so alpha is held to an absolute bar, a decade above the state's.
+    np.testing.assert_allclose(ag, ao, rtol=0, atol=100 * tol)
 
 
 def test_free_stream_preserved_on_gpu(cg, orc):
