@@ -37,6 +37,12 @@ FLUX_FLOPS_PER_GP_NS = 4983
 FLUX_FLOPS_PER_GP_EULER = 4948
 MI355X_FP64_VECTOR_TFLOPS = 78.6
 
+# HBM bytes moved by one launch of the flux kernel on each workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs of this script, scaled by
+# the counters' reading for a plain copy of known size (FETCH x2.0, WRITE x1.0).
+# Valid only for the kernel source they were taken with; None when not taken.
+FLUX_TRAFFIC_BYTES = {"cylinder_ns_mach8_131k": 125.6e6}
+
 
 def workload(name):
     import synthmesh as sm
@@ -123,7 +129,8 @@ def main():
     achieved = fpg * n_gp / (flux_ms / 1e3) / 1e12
     roof = {"bound": "alu", "kernel": "k_flux<2>", "achieved": achieved,
             "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": None,
+            "frac": achieved / MI355X_FP64_VECTOR_TFLOPS,
+            "traffic": FLUX_TRAFFIC_BYTES.get(args.workload),
             "avg_ms": flux_ms, "work_items": n_gp, "flops_per_item": fpg}
 
     out = {"metric": METRIC, "value": value, "unit": "Mcell·V-cycles/s", "n_gpus": 1,

@@ -96,6 +96,11 @@ typedef struct cgks_params {
     double skew_limit;         /* Alg. 3 minimum sin(skewness angle), default 0.2 */
     double slope_relax;        /* theta of the fine slope update grad <- grad + theta (grad_new - grad);
                                   1 = full replacement (Sec. 2.4); same fixed point for any theta in (0,1] */
+    double update_limit;       /* kappa of the update safeguard of coarse LU-SGS updates and prolongation
+                                  corrections: each cell applies the largest fraction 1, 1/2, ..., 2^-10
+                                  (else 0) of its update that keeps rho and p positive and at least
+                                  (1 - kappa) times their current values; kappa <= 0 applies an update
+                                  whole if rho, p stay positive, else not at all.  Default 0.5 */
 } cgks_params;
 
 /* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).
@@ -285,7 +290,8 @@ int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, floa
 int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, const float* fstd, const float* tmean,
                        const float* tstd, int* n_fallback);
 
-/* Counters: positivity-guard hits of the reconstruction, prolongation skips. */
+/* Counters: positivity-guard hits of the reconstruction; prolongation
+ * corrections applied only in part or not at all by the update safeguard. */
 int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);
 
 #ifdef __cplusplus

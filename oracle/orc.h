@@ -47,6 +47,7 @@ typedef struct orc_params {
     double lusgs_omega;
     double skew_limit;
     double slope_relax;
+    double update_limit;
 } orc_params;
 
 typedef struct orc_mesh {

@@ -81,6 +81,39 @@ bool physical(const orc_params& p, const double* W) {
     return rho > 0.0 && pr > 0.0;
 }
 
+/* Internal energy density rho e = E - |m|^2 / (2 rho) (proportional to p). */
+double rho_e(int dim, const double* W) {
+    double ke = 0.0;
+    for (int d = 0; d < dim; ++d) ke = ke + W[1 + d] * W[1 + d];
+    return W[dim + 1] - 0.5 * ke / W[0];
+}
+
+/* Fraction theta of an update dW that is applied to W (the paper states no
+ * safeguard for coarse updates or corrections).  kappa <= 0: theta = 1 when
+ * W + dW has rho > 0 and p > 0, else 0.  kappa > 0: the largest theta of
+ * 1, 1/2, ..., 2^-10 for which rho and rho e of W + theta dW are positive and
+ * at least (1 - kappa) times those of W; 0 when none is. */
+double update_fraction(const orc_params& p, const double* W, const double* dW) {
+    const int dim = p.dim, nv = dim + 2;
+    double Wn[5];
+    if (!(p.update_limit > 0.0)) {
+        for (int q = 0; q < nv; ++q) Wn[q] = W[q] + dW[q];
+        return (Wn[0] > 0.0 && rho_e(dim, Wn) > 0.0) ? 1.0 : 0.0;
+    }
+    const double lo_r = (1.0 - p.update_limit) * W[0];
+    const double lo_e = (1.0 - p.update_limit) * rho_e(dim, W);
+    double th = 1.0;
+    for (int m = 0; m <= 10; ++m) {
+        for (int q = 0; q < nv; ++q) Wn[q] = W[q] + th * dW[q];
+        if (Wn[0] > 0.0 && Wn[0] >= lo_r) {
+            const double e = rho_e(dim, Wn);
+            if (e > 0.0 && e >= lo_e) return th;
+        }
+        th = 0.5 * th;
+    }
+    return 0.0;
+}
+
 /* Build the reconstruction of fine cell i from the current state (Sec. 3). */
 void build_rec(orc_ctx* c, int i, CellRec& r) {
     const int dim = c->dim, nv = c->nvar;
@@ -382,7 +415,11 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
                 for (int q = 0; q < nv; ++q) L.dW[i * nv + q] -= 0.5 * al[i] * s[q] / D[i];
             }
     }
-    for (size_t k = 0; k < L.W.size(); ++k) L.W[k] += L.dW[k];
+    for (int i = 0; i < L.n; ++i) {
+        const double th = update_fraction(p, &L.W[i * nv], &L.dW[i * nv]);
+        if (th > 0.0)
+            for (int q = 0; q < nv; ++q) L.W[i * nv + q] += th * L.dW[i * nv + q];
+    }
 }
 
 /* New slopes of the fine step: grad <- grad + theta (grad_new - grad).  theta = 1
@@ -393,14 +430,20 @@ void relax_slopes(orc_ctx* c, const std::vector<double>& gnew) {
     for (size_t k = 0; k < g.size(); ++k) g[k] = g[k] + th * (gnew[k] - g[k]);
 }
 
-/* Explicit fine step of Eq. smo (local time step, Res = -R). */
+/* Explicit fine step of Eq. smo (local time step, Res = -R), applied through
+ * update_fraction (a cell takes a fraction theta of its step). */
 void fine_step(orc_ctx* c) {
     Level& L0 = c->lv[0];
     const int nv = c->nvar;
     std::vector<double> R, g, a, dte;
     fine_residual(c, R, g, a, dte);
-    for (int i = 0; i < L0.n; ++i)
-        for (int q = 0; q < nv; ++q) L0.W[i * nv + q] -= dte[i] / L0.V[i] * R[i * nv + q];
+    for (int i = 0; i < L0.n; ++i) {
+        double dW[5];
+        for (int q = 0; q < nv; ++q) dW[q] = -(dte[i] / L0.V[i] * R[i * nv + q]);
+        const double th = update_fraction(c->p, &L0.W[i * nv], dW);
+        if (th > 0.0)
+            for (int q = 0; q < nv; ++q) L0.W[i * nv + q] += th * dW[q];
+    }
     relax_slopes(c, g);
     L0.alpha = a;
 }
@@ -443,6 +486,8 @@ void restrict_level(orc_ctx* c, int l, const std::vector<double>& res_fine) {
     for (size_t k = 0; k < Res.size(); ++k) G.F[k] = G.Rstar[k] - Res[k];
 }
 
+/* Prolongation (Eq. prolongation): the DF-weighted injected coarse correction,
+ * applied through update_fraction; cells with theta < 1 are counted. */
 void prolong_level(orc_ctx* c, int l) {
     const int nv = c->nvar;
     Level& F = c->lv[l];
@@ -450,12 +495,12 @@ void prolong_level(orc_ctx* c, int l) {
     for (int i = 0; i < F.n; ++i) {
         int I = F.parent[i];
         double a = c->p.df_prolong ? F.alpha[i] : 1.0;
-        double Wn[5];
-        for (int q = 0; q < nv; ++q) Wn[q] = F.W[i * nv + q] + a * (G.W[I * nv + q] - G.W0[I * nv + q]);
-        if (physical(c->p, Wn))
-            for (int q = 0; q < nv; ++q) F.W[i * nv + q] = Wn[q];
-        else
-            ++c->prolong_skips;
+        double dW[5];
+        for (int q = 0; q < nv; ++q) dW[q] = a * (G.W[I * nv + q] - G.W0[I * nv + q]);
+        const double th = update_fraction(c->p, &F.W[i * nv], dW);
+        if (th > 0.0)
+            for (int q = 0; q < nv; ++q) F.W[i * nv + q] += th * dW[q];
+        if (th < 1.0) ++c->prolong_skips;
     }
 }
 

@@ -86,6 +86,7 @@ void make_kparams(cgks_ctx* c) {
     k.eps = p.weno_eps;
     k.omega = p.lusgs_omega;
     k.slope_relax = p.slope_relax;
+    k.update_limit = p.update_limit;
     k.df_relax = p.df_relax;
     k.df_prolong = p.df_prolong;
     const double a = p.aoa_deg * M_PI / 180.0;
@@ -416,6 +417,7 @@ void cgks_default_params(cgks_params* p) {
     p->lusgs_omega = 1.0;
     p->skew_limit = 0.2;
     p->slope_relax = 1.0;
+    p->update_limit = 0.5;
 }
 
 const char* cgks_strerror(int code) {
@@ -440,6 +442,7 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
         return CGKS_EINVAL;
     if (p->precision != CGKS_FP64 && p->precision != CGKS_MIXED) return CGKS_EINVAL;
     if (!(p->slope_relax > 0.0 && p->slope_relax <= 1.0)) return CGKS_EINVAL;
+    if (!(p->update_limit <= 1.0)) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
@@ -840,6 +843,7 @@ bool same_shared_params(const cgks_params& a, const cgks_params& b) {
            a.precision == b.precision && a.tau_c1 == b.tau_c1 && a.tau_c2 == b.tau_c2 &&
            a.weno_gamma_large == b.weno_gamma_large && a.weno_eps == b.weno_eps &&
            a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
+           a.update_limit == b.update_limit &&
            ((a.reynolds > 0.0) == (b.reynolds > 0.0));
 }
 

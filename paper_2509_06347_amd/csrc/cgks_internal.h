@@ -104,7 +104,7 @@ struct Workspace {
 struct KParams {
     int dim;
     double gamma, K, prandtl, mach, reynolds, mu_inf, Tinf, S_suth, Tw;
-    double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax;
+    double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax, update_limit;
     int df_relax, df_prolong;
     double u_inf[3];
 };

@@ -371,6 +371,47 @@ __device__ __forceinline__ double block_sum(double v) {
     return sh[0];
 }
 
+/* Internal energy density rho e = E - |m|^2 / (2 rho), proportional to p. */
+template <int D>
+__device__ __forceinline__ double rho_e_plain(const double* W) {
+#pragma clang fp contract(off)
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ke = ke + W[1 + d] * W[1 + d];
+    return W[D + 1] - 0.5 * ke / W[0];
+}
+
+/* Fraction of the update dW that a cell applies (no safeguard is stated in
+ * the paper): kappa <= 0 takes all of dW when rho and p stay positive, else
+ * none; kappa > 0 takes the largest of 1, 1/2, ..., 2^-10 that keeps rho and
+ * rho e positive and at least (1 - kappa) times their current values, else
+ * none.  Evaluated without contraction so that its decisions match a plain
+ * FP64 evaluation. */
+template <int D>
+__device__ double update_fraction(const double* W, const double* dW, double kappa) {
+#pragma clang fp contract(off)
+    constexpr int NV = D + 2;
+    double Wn[NV];
+    if (!(kappa > 0.0)) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wn[q] = W[q] + dW[q];
+        return (Wn[0] > 0.0 && rho_e_plain<D>(Wn) > 0.0) ? 1.0 : 0.0;
+    }
+    const double lo_r = (1.0 - kappa) * W[0];
+    const double lo_e = (1.0 - kappa) * rho_e_plain<D>(W);
+    double th = 1.0;
+    for (int m = 0; m <= 10; ++m) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wn[q] = W[q] + th * dW[q];
+        if (Wn[0] > 0.0 && Wn[0] >= lo_r) {
+            const double e = rho_e_plain<D>(Wn);
+            if (e > 0.0 && e >= lo_e) return th;
+        }
+        th = 0.5 * th;
+    }
+    return 0.0;
+}
+
 template <int D>
 __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mode, double* partial, int* status) {
     using S = Shape<D>;
@@ -426,10 +467,18 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
         } else {
             const double dtv = f.dt[i] / V;
             const double th = kp.slope_relax;
-            double Wn[NV];
+            double Wo[NV], dW[NV], Wn[NV];
+            bool finite = true;
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
-                Wn[q] = f.W[q * n + i] - dtv * R[q];
+                Wo[q] = f.W[q * n + i];
+                dW[q] = -(dtv * R[q]);
+                finite = finite && isfinite(dW[q]);
+            }
+            const double fr = update_fraction<D>(Wo, dW, kp.update_limit);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                Wn[q] = fr > 0.0 ? Wo[q] + fr * dW[q] : Wo[q];
                 f.W[q * n + i] = Wn[q];
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
@@ -440,7 +489,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
             f.alpha[i] = a;
             Prim P;
             primitive<D>(kp, Wn, P);
-            if (!(P.rho > 0.0 && P.p > 0.0 && isfinite(Wn[D + 1]))) atomicOr(status, 1);
+            if (!(finite && P.rho > 0.0 && P.p > 0.0 && isfinite(Wn[D + 1]))) atomicOr(status, 1);
             if (mode == FINE_STEP_NORM) {
                 const double r = R[0] / V;
                 contrib = r * r;
@@ -654,13 +703,6 @@ __global__ void __launch_bounds__(BLOCK) k_lusgs(CoarseDev c, KParams kp, int lo
     }
 }
 
-template <class T>
-__global__ void __launch_bounds__(BLOCK) k_add(double* W, const double* dWraw, int m) {
-    const T* dW = reinterpret_cast<const T*>(dWraw);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < m) W[t] += (double)dW[t];
-}
-
 /* Restriction (Sec. 5.2): W0 = sum V W / V_c (FP64), Res* = sum Res (in T),
  * alpha = min. */
 template <int D, class T>
@@ -700,32 +742,49 @@ __global__ void __launch_bounds__(BLOCK) k_restrict(CoarseDev c, const double* W
 }
 
 /* DF-limited prolongation (Eq. prolongation) with injection; the correction
- * alpha (W - W0) is formed in T.  A correction that would make rho or p
- * non-positive is skipped. */
+ * alpha (W - W0) is formed in T and applied through update_fraction; cells
+ * that apply less than all of it are counted. */
 template <int D, class T>
 __global__ void __launch_bounds__(BLOCK) k_prolong(CoarseDev c, double* Wf, const double* af, int nfine,
-                                                  int df, unsigned long long* skips) {
+                                                  int df, double kappa, unsigned long long* skips) {
     constexpr int NV = D + 2;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nfine) return;
     const int I = c.parent[i];
     const int n = c.n;
     const T a = df ? (T)af[i] : (T)1;
-    double Wn[NV];
+    double W[NV], dW[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         const T dl = (T)(c.W[q * n + I] - c.W0[q * n + I]);
-        Wn[q] = Wf[q * nfine + i] + (double)(a * dl);
+        dW[q] = (double)(a * dl);
+        W[q] = Wf[q * nfine + i];
     }
-    double ke = 0.0;
+    const double th = update_fraction<D>(W, dW, kappa);
+    if (th > 0.0) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) ke += Wn[1 + d] * Wn[1 + d];
-    const double p = Wn[D + 1] - 0.5 * ke / Wn[0];
-    if (Wn[0] > 0.0 && p > 0.0) {
+        for (int q = 0; q < NV; ++q) Wf[q * nfine + i] = W[q] + th * dW[q];
+    }
+    if (th < 1.0) atomicAdd(skips, 1ull);
+}
+
+/* Coarse LU-SGS update W += theta dW per cell (dW in T). */
+template <int D, class T>
+__global__ void __launch_bounds__(BLOCK) k_coarse_add(double* Wc, const double* dWraw, int n, double kappa) {
+    constexpr int NV = D + 2;
+    const T* dWc = reinterpret_cast<const T*>(dWraw);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double W[NV], dW[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Wf[q * nfine + i] = Wn[q];
-    } else {
-        atomicAdd(skips, 1ull);
+    for (int q = 0; q < NV; ++q) {
+        W[q] = Wc[q * n + i];
+        dW[q] = (double)dWc[q * n + i];
+    }
+    const double th = update_fraction<D>(W, dW, kappa);
+    if (th > 0.0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wc[q * n + i] = W[q] + th * dW[q];
     }
 }
 
@@ -826,9 +885,16 @@ void launch_lusgs(cgks_ctx* c, int level) {
 
 void launch_coarse_update(cgks_ctx* c, int level) {
     CoarseDev& L = c->coarse[level - 1];
-    const int m = L.n * c->nv;
-    if (c->p.precision == CGKS_MIXED) k_add<float><<<nblk(m), BLOCK, 0, c->stream>>>(L.W, L.dW, m);
-    else k_add<double><<<nblk(m), BLOCK, 0, c->stream>>>(L.W, L.dW, m);
+    const bool mx = c->p.precision == CGKS_MIXED;
+    const int nb = nblk(L.n);
+    const double kap = c->kp.update_limit;
+    if (c->dim == 2) {
+        if (mx) k_coarse_add<2, float><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        else k_coarse_add<2, double><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+    } else {
+        if (mx) k_coarse_add<3, float><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        else k_coarse_add<3, double><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+    }
 }
 
 void launch_restrict(cgks_ctx* c, int level) {
@@ -865,13 +931,14 @@ void launch_prolong(cgks_ctx* c, int level) {
     }
     const bool mx = c->p.precision == CGKS_MIXED;
     const int nb = nblk(nfine), df = c->kp.df_prolong;
+    const double kap = c->kp.update_limit;
     unsigned long long* sk = c->ws.skips;
     if (c->dim == 2) {
-        if (mx) k_prolong<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
-        else k_prolong<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+        if (mx) k_prolong<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        else k_prolong<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
     } else {
-        if (mx) k_prolong<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
-        else k_prolong<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, sk);
+        if (mx) k_prolong<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        else k_prolong<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
     }
 }
 

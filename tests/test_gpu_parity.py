@@ -157,6 +157,35 @@ def test_vcycle_trajectory_parity(cg, orc, case):
     np.testing.assert_allclose(ag, ao, rtol=0, atol=100 * tol)
 
 
+@pytest.mark.parametrize("kappa", [0.5, 0.0])
+def test_update_limit_parity(cg, orc, kappa):
+    """Coarse LU-SGS under a forcing large enough to engage the update safeguard,
+    then a prolongation of the resulting correction: same fractions as the oracle."""
+    mesh = sm.annulus(12, 4, jitter=0.15, seed=11, nref=2, wall_tag=sm.SLIP)
+    g, o = _pair(cg, orc, mesh, mach=0.5, update_limit=kappa)
+    W, grad, alpha = _perturbed(mesh, o, 0.5, seed=8)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+        s.smooth(0, 1)
+        s.restrict(0)
+    V1, _ = o.cell_geometry(1)
+    F = o.get_level_state(1)[2].copy()
+    F[:, 0] -= 30.0 * V1
+    for s in (g, o):
+        s.set_level_state(1, F=F)
+        s.smooth(1, 2)
+    Wg, Wo = g.get_level_state(1)[0], o.get_level_state(1)[0]
+    assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
+    sk = []
+    for s in (g, o):
+        s.prolong(0)
+        sk.append(s.stats()[1])
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
+    assert sk[0] == sk[1]
+
+
 def test_free_stream_preserved_on_gpu(cg, orc):
     mesh = sm.annulus(13, 5, jitter=0.2, seed=3, nref=2, wall_tag=sm.FARFIELD)
     g = cg.Solver(mesh, n_levels=3, mach=0.7, aoa_deg=12.0)

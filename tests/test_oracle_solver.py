@@ -209,3 +209,53 @@ def test_vcycle_is_stable_on_agglomerated_levels(orc):
     o.init_freestream()
     norms = [o.vcycle() for _ in range(5)]
     assert all(np.isfinite(norms)) and norms[-1] < norms[0]
+
+
+def _rho_e(W):
+    return W[:, 3] - 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0]
+
+
+@pytest.mark.parametrize("kappa,drho,theta", [
+    (0.5, -0.3, 1.0),     # rho 0.7 >= 0.5: whole correction
+    (0.5, -0.8, 0.5),     # rho 0.2 < 0.5, half -> 0.6
+    (0.5, -1.5, 0.25),    # 1 and 1/2 fail, a quarter -> 0.625
+    (0.0, -0.8, 1.0),     # kappa 0: whole while rho, p stay positive
+    (0.0, -1.2, 0.0),     # kappa 0: skipped when rho would be negative
+])
+def test_prolongation_update_limit_closed_form(orc, ff_mesh, kappa, drho, theta):
+    """The update safeguard on the injected correction, against hand-computed
+    fractions: with momentum and energy unchanged, rho e also stays above half."""
+    o = orc.Oracle(ff_mesh, n_levels=2, mach=0.5, df_prolong=0, update_limit=kappa)
+    o.init_freestream()
+    W, _, _ = o.get_state()
+    _, W0c, _, _ = o.get_level_state(1)
+    Wc = W0c.copy()
+    Wc[:, 0] = W0c[:, 0] + drho
+    o.set_level_state(1, W=Wc, W0=W0c)
+    skips0 = o.stats()[1]
+    o.prolong(0)
+    W2, _, _ = o.get_state()
+    d = (W0c[0, 0] + drho) - W0c[0, 0]          # the correction as the oracle forms it
+    expect = W.copy()
+    expect[:, 0] = W[:, 0] + theta * d
+    assert np.array_equal(W2, expect)
+    assert o.stats()[1] - skips0 == (0 if theta == 1.0 else len(W))
+
+
+@pytest.mark.parametrize("scale", [1.0, 30.0, 1e3])
+def test_lusgs_update_limit_bounds_the_drop(orc, small_mesh, scale):
+    """A large mass-sink forcing on level 1: no cell loses more than kappa = 1/2
+    of its rho or rho e in one LU-SGS iteration, and the level still moves."""
+    o = _prepared(orc, small_mesh, mach=0.5, update_limit=0.5)
+    o.smooth(0, 1)
+    o.restrict(0)
+    W, W0, F, a = o.get_level_state(1)
+    V1, _ = o.cell_geometry(1)
+    F2 = F.copy()
+    F2[:, 0] -= scale * V1
+    o.set_level_state(1, F=F2)
+    o.smooth(1, 1)
+    W1 = o.get_level_state(1)[0]
+    assert np.all(W1[:, 0] >= 0.5 * W[:, 0])
+    assert np.all(_rho_e(W1) >= 0.5 * _rho_e(W))
+    assert np.abs(W1 - W).max() > 0
