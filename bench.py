@@ -41,7 +41,7 @@ MI355X_FP64_VECTOR_TFLOPS = 78.6
 # rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs of this script, scaled by
 # the counters' reading for a plain copy of known size (FETCH x2.0, WRITE x1.0).
 # Valid only for the kernel source they were taken with; None when not taken.
-FLUX_TRAFFIC_BYTES = {"cylinder_ns_mach8_131k": 125.6e6}
+FLUX_TRAFFIC_BYTES = {}
 
 
 def workload(name):

@@ -461,8 +461,11 @@ void ghost(const orc_params& p, int tag, const double* W, const double* g, const
             rb = rho; pb = pr;
             for (int d = 0; d < 3; ++d) Ub[d] = U[d];
         } else {
+            /* subsonic: entropy and tangential velocity from the interior where the
+             * free stream leaves the domain (u_inf . n > 0), else from the free
+             * stream; a fixed choice per face */
             double s, Ut[3];
-            if (ub > 0.0) {
+            if (uni > 0.0) {
                 s = pr / std::pow(rho, gm);
                 for (int d = 0; d < dim; ++d) Ut[d] = U[d] - un * n[d];
             } else {

@@ -249,29 +249,55 @@ int upload(cgks_ctx* c) {
     f.nb = (dim == 2) ? 5 : 9;
     const int n = f.n, nf = f.nf, ng = f.ngp, ns = f.nslot, nq = f.nb;
     const int ncol = ns * (1 + dim);
-    std::vector<double> Cs((size_t)dim * n), fn((size_t)dim * nf), fS(nf), fgp((size_t)ng * dim * nf);
-    std::vector<int> sface((size_t)ns * n), snbr((size_t)ns * n), fL(nf), fR(nf), ftag(nf);
+    std::vector<double> Cs((size_t)dim * n), fn((size_t)dim * nf), fS(nf);
+    std::vector<int> sface((size_t)ns * n), snbr((size_t)ns * n), fL(nf), fR(nf), fsl(nf);
+    std::vector<int> stag((size_t)ns * n);
+    std::vector<double> sS((size_t)ns * n), sn((size_t)dim * ns * n), sX((size_t)ng * dim * ns * n);
     for (int i = 0; i < n; ++i)
         for (int d = 0; d < dim; ++d) Cs[(size_t)d * n + i] = H.C[(size_t)i * dim + d];
-    for (int k = 0; k < nf; ++k) {
-        const HFace& F = H.faces[k];
-        fL[k] = F.L;
-        fR[k] = F.R;
-        ftag[k] = F.tag;
-        fS[k] = F.S;
-        for (int d = 0; d < dim; ++d) {
-            fn[(size_t)d * nf + k] = F.n[d];
-            for (int g = 0; g < ng; ++g) fgp[((size_t)g * dim + d) * nf + k] = F.gp[g][d];
-        }
-    }
+    /* device face order: by owner cell L, then by the face's slot in L */
+    std::vector<int>& fperm = c->fperm;
+    std::vector<int> finv(nf, -1), slotL(nf, 0), slotR(nf, 7);
+    fperm.clear();
     for (int i = 0; i < n; ++i)
+        for (int s = 0; s < ns; ++s) {
+            const int k = H.cf[i][s];
+            if (H.faces[k].L == i) {
+                slotL[k] = s;
+                finv[k] = (int)fperm.size();
+                fperm.push_back(k);
+            } else {
+                slotR[k] = s;
+            }
+        }
+    if ((int)fperm.size() != nf) return fail(c, CGKS_EMESH, "face without an owner cell");
+    for (int e = 0; e < nf; ++e) {
+        const HFace& F = H.faces[fperm[e]];
+        fL[e] = F.L;
+        fR[e] = F.R;
+        fS[e] = F.S;
+        fsl[e] = slotL[fperm[e]] | (slotR[fperm[e]] << 3);
+        for (int d = 0; d < dim; ++d) fn[(size_t)d * nf + e] = F.n[d];
+    }
+    for (int i = 0; i < n; ++i) {
+        const double ih = 1.0 / H.h[i];
         for (int s = 0; s < ns; ++s) {
             const int k = H.cf[i][s];
             const HFace& F = H.faces[k];
             const int side = (F.L == i) ? 0 : 1;
-            sface[(size_t)s * n + i] = k * 2 + side;
-            snbr[(size_t)s * n + i] = (F.R < 0) ? -1 : (side ? F.L : F.R);
+            const double sg = side ? -1.0 : 1.0;
+            const size_t o = (size_t)s * n + i;
+            sface[o] = finv[k] * 2 + side;
+            snbr[o] = (F.R < 0) ? -1 : (side ? F.L : F.R);
+            stag[o] = F.R < 0 ? F.tag : 0;
+            sS[o] = F.S;
+            for (int d = 0; d < dim; ++d) {
+                sn[((size_t)d * ns + s) * n + i] = sg * F.n[d];
+                for (int g = 0; g < ng; ++g)
+                    sX[(((size_t)g * dim + d) * ns + s) * n + i] = (F.gp[g][d] - H.C[(size_t)i * dim + d]) * ih;
+            }
         }
+    }
     TRY(dalloc(c, &f.V, n)); TRY(h2d(c, f.V, H.V));
     TRY(dalloc(c, &f.C, (size_t)dim * n)); TRY(h2d(c, f.C, Cs));
     TRY(dalloc(c, &f.h, n)); TRY(h2d(c, f.h, H.h));
@@ -279,19 +305,23 @@ int upload(cgks_ctx* c) {
     TRY(dalloc(c, &f.op, (size_t)nq * ncol * n)); TRY(h2d(c, f.op, H.op));
     TRY(dalloc(c, &f.slot_face, (size_t)ns * n)); TRY(h2d(c, f.slot_face, sface));
     TRY(dalloc(c, &f.slot_nbr, (size_t)ns * n)); TRY(h2d(c, f.slot_nbr, snbr));
+    TRY(dalloc(c, &f.slot_tag, (size_t)ns * n)); TRY(h2d(c, f.slot_tag, stag));
+    TRY(dalloc(c, &f.slot_S, (size_t)ns * n)); TRY(h2d(c, f.slot_S, sS));
+    TRY(dalloc(c, &f.slot_n, (size_t)dim * ns * n)); TRY(h2d(c, f.slot_n, sn));
+    TRY(dalloc(c, &f.slot_X, (size_t)ng * dim * ns * n)); TRY(h2d(c, f.slot_X, sX));
     TRY(dalloc(c, &f.fL, nf)); TRY(h2d(c, f.fL, fL));
     TRY(dalloc(c, &f.fR, nf)); TRY(h2d(c, f.fR, fR));
-    TRY(dalloc(c, &f.ftag, nf)); TRY(h2d(c, f.ftag, ftag));
+    TRY(dalloc(c, &f.fslot, nf)); TRY(h2d(c, f.fslot, fsl));
     TRY(dalloc(c, &f.fn, (size_t)dim * nf)); TRY(h2d(c, f.fn, fn));
     TRY(dalloc(c, &f.fS, nf)); TRY(h2d(c, f.fS, fS));
-    TRY(dalloc(c, &f.fgp, (size_t)ng * dim * nf)); TRY(h2d(c, f.fgp, fgp));
     TRY(dalloc(c, &f.W, (size_t)nv * n));
     TRY(dalloc(c, &f.grad, (size_t)nv * dim * n));
     TRY(dalloc(c, &f.alpha, n));
     TRY(dalloc(c, &f.Wsave, (size_t)nv * n));
     TRY(dalloc(c, &f.gsave, (size_t)nv * dim * n));
     TRY(dalloc(c, &f.asave, n));
-    TRY(dalloc(c, &f.gpst, (size_t)2 * ng * nv * (1 + dim) * nf));
+    TRY(dalloc(c, &f.gps, (size_t)ng * nv * (1 + dim) * n * ns));
+    TRY(dalloc(c, &f.gho, (size_t)ng * nv * (1 + dim) * nf));
     TRY(dalloc(c, &f.fF, (size_t)nv * ng * nf));
     TRY(dalloc(c, &f.fG, (size_t)nv * ng * nf));
     TRY(dalloc(c, &f.fa, (size_t)ng * nf));
@@ -784,7 +814,7 @@ int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
 extern "C" int cgks_autotune(cgks_ctx* c) {
     TRY(check_level(c, 0));
     /* launch shape of each fine kernel: the fastest candidate at the current state */
-    static const int cand[3][3] = {{64, 128, 0}, {64, 128, 256}, {64, 128, 256}};
+    static const int cand[3][3] = {{32, 64, 0}, {64, 128, 256}, {64, 128, 256}};  /* recon: cells per block */
     int best[3] = {c->blk_recon, c->blk_flux, c->blk_gather};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -989,7 +1019,7 @@ int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out) {
     }
     std::vector<int> hp(m->hl[0].n), hf(m->hl[0].faces.size());
     for (int i = 0; i < m->hl[0].n; ++i) hp[i] = owner(0, i);
-    for (size_t f = 0; f < hf.size(); ++f) hf[f] = owner(0, m->hl[0].faces[f].L);
+    for (size_t f = 0; f < hf.size(); ++f) hf[f] = owner(0, m->hl[0].faces[m->fperm[f]].L);
     if ((rc = dalloc(c, &pid, hp.size())) || (rc = h2d(c, pid, hp)) || (rc = dalloc(c, &fpid, hf.size())) ||
         (rc = h2d(c, fpid, hf)) || (rc = dalloc(c, &poff, n + 1)) || (rc = h2d(c, poff, B->coff[0])) ||
         (rc = dalloc(c, &r2, m->hl[0].n))) {

@@ -49,17 +49,23 @@ struct HLevel {
 
 /* --------------------------------------------------------------- device --- */
 
-/* Fine level, structure of arrays with the cell (or face) index fastest. */
+/* Fine level, structure of arrays with the cell (or face) index fastest.
+ * Device faces are numbered by (owner cell L, slot of the face in L). */
 struct FineDev {
     int n, nf, ngp, nslot, nb;
     double *V, *C, *h, *mean0, *op;   /* op: [nb][nslot*(1+dim)][n] */
     int *slot_face;                   /* [nslot][n]: face id * 2 + side (side 1 = cell is R) */
     int *slot_nbr;                    /* [nslot][n]: neighbour or -1 */
-    int *fL, *fR, *ftag;
-    double *fn, *fS, *fgp;            /* fn [dim][nf], fgp [ngp][dim][nf] */
+    int *slot_tag;                    /* [nslot][n]: boundary tag of the slot's face (0 interior) */
+    double *slot_S, *slot_n;          /* [nslot][n] face area, [dim][nslot][n] outward unit normal */
+    double *slot_X;                   /* [ngp][dim][nslot][n] Gauss points (x - x_c) / h */
+    int *fL, *fR;
+    int *fslot;                       /* per face: slot in L | (slot in R, 7 on a boundary) << 3 */
+    double *fn, *fS;                  /* fn [dim][nf] */
     double *W, *grad, *alpha;         /* state */
     double *Wsave, *gsave, *asave;    /* start-of-cycle copy for roll-back */
-    double *gpst;                     /* [2][ngp][nv + nv*dim][nf] Gauss-point states */
+    double *gps;                      /* [ngp][nv + nv*dim][n][nslot] Gauss-point states of each cell's side */
+    double *gho;                      /* [ngp][nv + nv*dim][nf] ghost states of boundary faces */
     double *fF, *fG, *fa;             /* [nv][ngp*nf], [nv][ngp*nf], [ngp*nf] */
     double *R, *gnew, *anew, *dt, *dti;
     double *res;                      /* -R of the restriction evaluation */
@@ -130,7 +136,8 @@ struct cgks_ctx {
     hipGraph_t graph_tmpl = nullptr;
     int cycles_done = 0;
     /* launch shapes chosen by the autotuner */
-    int blk_recon = 128, blk_flux = 256, blk_gather = 256;
+    int blk_recon = 64, blk_flux = 256, blk_gather = 256;   /* recon: cells per block */
+    std::vector<int> fperm;               /* device face -> host face of level 0 */
 };
 
 namespace cgks {

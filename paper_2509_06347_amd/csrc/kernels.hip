@@ -28,6 +28,9 @@
 namespace cgks {
 
 constexpr int BLOCK = 256;
+/* Coarse levels hold 8k-33k cells per colour sweep or less: small blocks spread
+ * them over all 256 compute units. */
+constexpr int CBLOCK = 64;
 
 /* Parameters of the problem that owns item idx (batched solves); the shared
  * parameters come from kp itself. */
@@ -115,209 +118,200 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
     }
 }
 
-constexpr int RBLOCK = 128;   /* reconstruction block: per-thread LDS columns */
-
+/* Reconstruction in two phases per block of `cells` cells (blockDim = cells x
+ * faces x Gauss points).  Phase 1, one thread per (cell, component): the p^2
+ * coefficients from the operator, the alpha-scaled Green-Gauss gradient and
+ * the nonlinear weights, into LDS; the component-0 thread also forms the local
+ * time steps.  Phase 2, one thread per (cell, face slot, Gauss point): value
+ * and gradient of every component at its point; the cell's positivity guard
+ * is an LDS flag over its points; states are written [k][component][cell][slot]
+ * and boundary slots add their ghost state.  Per cell and component the
+ * arithmetic is that of a one-thread-per-cell evaluation. */
+constexpr int RMAXC = 64;   /* most cells per reconstruction block */
 template <int D>
-__global__ void __launch_bounds__(RBLOCK) k_recon(FineDev f, KParams kp0) {
+__global__ void __launch_bounds__(1024) k_recon2(FineDev f, KParams kp0, int cells) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NC = S::NC, NCOL = S::NCOL;
-    constexpr int NK = NQ + D;                    /* coefficients per component */
-    /* Polynomial coefficients live in LDS, one column per thread (no sharing, no
-     * barriers): keeps the kernel free of register spills. */
-    __shared__ double sc[NV * NK][RBLOCK];
+    constexpr int NK = NQ + D;
+    __shared__ double coef[NV * NK][RMAXC];
+    __shared__ int bad[RMAXC];
     const int t = threadIdx.x;
-    const int i = blockIdx.x * blockDim.x + t;
     const int n = f.n, nf = f.nf;
-    if (i >= n) return;
-    const KParams kp = localize(kp0, f.ptab, f.pid, i);
-    double W0[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) W0[q] = f.W[q * n + i];
-    const double V = f.V[i], h = f.h[i], al = f.alpha[i];
-    double xc[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) xc[d] = f.C[d * n + i];
+    const int i0 = blockIdx.x * cells;
 
-    int fid[NS], side[NS], nbr[NS], tag[NS];
-    double nout[NS][D], Sf[NS];
+    /* ---- phase 1: (cell, component) ---- */
+    if (t < cells * NV) {
+        const int cl = t % cells, q = t / cells;
+        const int i = i0 + cl;
+        if (q == 0) bad[cl] = 0;
+        if (i < n) {
+            const KParams kp = localize(kp0, f.ptab, f.pid, i);
+            double W0[NV];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int sf = f.slot_face[s * n + i];
-        fid[s] = sf >> 1;
-        side[s] = sf & 1;
-        nbr[s] = f.slot_nbr[s * n + i];
-        tag[s] = f.ftag[fid[s]];
-        Sf[s] = f.fS[fid[s]];
-        const double sg = side[s] ? -1.0 : 1.0;
+            for (int r = 0; r < NV; ++r) W0[r] = f.W[r * n + i];
+            const double V = f.V[i], h = f.h[i], al = f.alpha[i];
+            int nbr[NS];
+            double nout[NS][D], Sf[NS];
 #pragma unroll
-        for (int d = 0; d < D; ++d) nout[s][d] = sg * f.fn[d * nf + fid[s]];
-    }
-
-    /* local explicit time step: convective + viscous spectral radius */
-    {
-        Prim P;
-        primitive<D>(kp, W0, P);
-        const double c = sqrt(kp.gamma * P.p / P.rho);
-        double lam = 0.0, s2 = 0.0;
+            for (int s = 0; s < NS; ++s) {
+                nbr[s] = f.slot_nbr[s * n + i];
+                Sf[s] = f.slot_S[s * n + i];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            double un = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) un += P.U[d] * nout[s][d];
-            lam += Sf[s] * (fabs(un) + c);
-            s2 += Sf[s] * Sf[s];
-        }
-        if (kp.reynolds > 0.0)
-            lam += fmax(4.0 / 3.0, kp.gamma / kp.prandtl) * sutherland(kp, P.p / P.rho) / P.rho * s2 / V;
-        f.dt[i] = kp.cfl_exp * V / lam;
-        f.dti[i] = kp.cfl_imp * V / lam;
-    }
-
-    /* neighbour averages (ghost averages on boundary faces) for the sub-stencil */
-    double Wn[NS][NV];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        if (nbr[s] >= 0) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) Wn[s][q] = f.W[q * n + nbr[s]];
-        } else {
-            ghost_state<D, false>(kp, tag[s], W0, nullptr, nout[s], Wn[s], nullptr);
-        }
-    }
-    double mean[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) mean[k] = f.mean0[k * n + i];
-
-    /* per component: p^2 coefficients a, Green-Gauss gradient g (times h), weights;
-     * P = Q0 + sum_k c2_k (phi_k - mean_k) + sum_d c1_d X_d with X = (x - xc)/h */
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double a[NQ];
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) a[k] = 0.0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (nbr[s] < 0) continue;
-            const double dq = Wn[s][q] - W0[q];
-            double gs[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) gs[d] = f.grad[(q * D + d) * n + nbr[s]];
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                const double* o = f.op + (size_t)(k * NCOL + s * (1 + D)) * n + i;
-                double acc = o[0] * dq;
-#pragma unroll
-                for (int d = 0; d < D; ++d) acc += o[(size_t)(1 + d) * n] * gs[d];
-                a[k] += acc;
+                for (int d = 0; d < D; ++d) nout[s][d] = f.slot_n[(d * NS + s) * n + i];
             }
+            if (q == 0) {
+                Prim P;
+                primitive<D>(kp, W0, P);
+                const double c = sqrt(kp.gamma * P.p / P.rho);
+                double lam = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    double un = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) un += P.U[d] * nout[s][d];
+                    lam += Sf[s] * (fabs(un) + c);
+                    s2 += Sf[s] * Sf[s];
+                }
+                if (kp.reynolds > 0.0)
+                    lam += fmax(4.0 / 3.0, kp.gamma / kp.prandtl) * sutherland(kp, P.p / P.rho) / P.rho * s2 / V;
+                f.dt[i] = kp.cfl_exp * V / lam;
+                f.dti[i] = kp.cfl_imp * V / lam;
+            }
+            /* component q of the neighbour averages (ghost averages on boundary faces) */
+            double Wq[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (nbr[s] >= 0) {
+                    Wq[s] = f.W[q * n + nbr[s]];
+                } else {
+                    double Wg[NV];
+                    ghost_state<D, false>(kp, f.slot_tag[s * n + i], W0, nullptr, nout[s], Wg, nullptr);
+                    Wq[s] = Wg[q];
+                }
+            }
+            double mean[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) mean[k] = f.mean0[k * n + i];
+            double a[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) a[k] = 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (nbr[s] < 0) continue;
+                const double dq = Wq[s] - W0[q];
+                double gs[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) gs[d] = f.grad[(q * D + d) * n + nbr[s]];
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    const double* o = f.op + (size_t)(k * NCOL + s * (1 + D)) * n + i;
+                    double acc = o[0] * dq;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) acc += o[(size_t)(1 + d) * n] * gs[d];
+                    a[k] += acc;
+                }
+            }
+            double g[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) g[d] = 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double avg = (Wq[s] + W0[q]) / (2.0 * V);
+#pragma unroll
+                for (int d = 0; d < D; ++d) g[d] += avg * Sf[s] * nout[s][d];
+            }
+            double gg = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                g[d] *= al * h;
+                gg += g[d] * g[d];
+            }
+            const double b0 = beta_large<D>(a, mean);
+            const double b1 = gg;
+            const double tz = fabs(b0 - b1);
+            const double t0 = tz / (b0 + kp.eps), t1 = tz / (b1 + kp.eps);
+            const double w0 = kp.g_large * (1.0 + t0 * t0), w1 = kp.g_small * (1.0 + t1 * t1);
+            const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
+            const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) coef[q * NK + k][cl] = cp2 * a[k];
+#pragma unroll
+            for (int d = 0; d < D; ++d) coef[q * NK + NQ + d][cl] = cp1 * g[d];
         }
-        double g[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) g[d] = 0.0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const double avg = (Wn[s][q] + W0[q]) / (2.0 * V);
-#pragma unroll
-            for (int d = 0; d < D; ++d) g[d] += avg * Sf[s] * nout[s][d];
-        }
-        double gg = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            g[d] *= al * h;
-            gg += g[d] * g[d];
-        }
-        const double b0 = beta_large<D>(a, mean);
-        const double b1 = gg;
-        const double tz = fabs(b0 - b1);
-        const double t0 = tz / (b0 + kp.eps), t1 = tz / (b1 + kp.eps);
-        const double w0 = kp.g_large * (1.0 + t0 * t0), w1 = kp.g_small * (1.0 + t1 * t1);
-        const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
-        const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) sc[q * NK + k][t] = cp2 * a[k];
-#pragma unroll
-        for (int d = 0; d < D; ++d) sc[q * NK + NQ + d][t] = cp1 * g[d];
     }
+    __syncthreads();
 
-    const double ih = 1.0 / h;
-    /* value (and gradient) of the reconstruction at x */
-    auto eval = [&](const double* x, double* Wx, double (*gx)[D], bool grad) {
-        double X[3], phi[NQ], dphi[NQ][3];
+    /* ---- phase 2: (cell, slot, Gauss point) ---- */
+    const int cl = t % cells, j = t / cells;
+    const int s = j / NG, k = j - s * NG;
+    const int i = i0 + cl;
+    const bool live = i < n && j < NS * NG;
+    double Wx[NV], gx[NV][D], W0[NV];
+    if (live) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) X[d] = (x[d] - xc[d]) * ih;
+        for (int r = 0; r < NV; ++r) W0[r] = f.W[r * n + i];
+        const double ih = 1.0 / f.h[i];
+        double X[3], phi[NQ], dphi[NQ][3], mean[NQ];
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = f.slot_X[((k * D + d) * NS + s) * n + i];
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) mean[m] = f.mean0[m * n + i];
         basis_at<D>(X, phi, dphi);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             double v = W0[q];
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) v += sc[q * NK + k][t] * (phi[k] - mean[k]);
+            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * (phi[m] - mean[m]);
 #pragma unroll
-            for (int d = 0; d < D; ++d) v += sc[q * NK + NQ + d][t] * X[d];
+            for (int d = 0; d < D; ++d) v += coef[q * NK + NQ + d][cl] * X[d];
             Wx[q] = v;
-            if (grad) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    double gd = sc[q * NK + NQ + d][t];
+            for (int d = 0; d < D; ++d) {
+                double gd = coef[q * NK + NQ + d][cl];
 #pragma unroll
-                    for (int k = 0; k < NQ; ++k) gd += sc[q * NK + k][t] * dphi[k][d];
-                    gx[q][d] = gd * ih;
-                }
+                for (int m = 0; m < NQ; ++m) gd += coef[q * NK + m][cl] * dphi[m][d];
+                gx[q][d] = gd * ih;
             }
         }
-    };
-
-    /* positivity guard over all Gauss points of the cell */
-    bool guard = false;
+        const KParams kp = localize(kp0, f.ptab, f.pid, i);
+        Prim P;
+        primitive<D>(kp, Wx, P);
+        if (!(P.rho > 0.0 && P.p > 0.0)) atomicOr(&bad[cl], 1);
+    }
+    __syncthreads();
+    if (!live) return;
+    if (bad[cl]) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+        for (int q = 0; q < NV; ++q) {
+            Wx[q] = W0[q];
 #pragma unroll
-        for (int k = 0; k < NG; ++k) {
-            double x[D], Wx[NV], gx[NV][D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) x[d] = f.fgp[(k * D + d) * nf + fid[s]];
-            eval(x, Wx, gx, false);
-            Prim P;
-            primitive<D>(kp, Wx, P);
-            if (!(P.rho > 0.0 && P.p > 0.0)) guard = true;
+            for (int d = 0; d < D; ++d) gx[q][d] = 0.0;
         }
-    if (guard) atomicAdd(f.guard, 1ull);
-
+        if (j == 0) atomicAdd(f.guard, 1ull);
+    }
+    double* out = f.gps + ((size_t)(k * NC) * n + i) * NS + s;
+    const size_t cs = (size_t)n * NS;
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+    for (int q = 0; q < NV; ++q) out[q * cs] = Wx[q];
 #pragma unroll
-        for (int k = 0; k < NG; ++k) {
-            double x[D], Wx[NV], gx[NV][D];
+    for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int d = 0; d < D; ++d) x[d] = f.fgp[(k * D + d) * nf + fid[s]];
-            if (guard) {
+        for (int d = 0; d < D; ++d) out[(NV + q * D + d) * cs] = gx[q][d];
+    if (f.slot_nbr[s * n + i] < 0) {
+        const KParams kp = localize(kp0, f.ptab, f.pid, i);
+        double nout[D], Wg[NV], gg[NV][D];
 #pragma unroll
-                for (int q = 0; q < NV; ++q) {
-                    Wx[q] = W0[q];
+        for (int d = 0; d < D; ++d) nout[d] = f.slot_n[(d * NS + s) * n + i];
+        ghost_state<D, true>(kp, f.slot_tag[s * n + i], Wx, gx, nout, Wg, gg);
+        const int fid = f.slot_face[s * n + i] >> 1;
+        double* og = f.gho + (size_t)(k * NC) * nf + fid;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) gx[q][d] = 0.0;
-                }
-            } else {
-                eval(x, Wx, gx, true);
-            }
-            double* out = f.gpst + (size_t)((side[s] * NG + k) * NC) * nf + fid[s];
+        for (int q = 0; q < NV; ++q) og[(size_t)q * nf] = Wg[q];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) out[(size_t)q * nf] = Wx[q];
+        for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int q = 0; q < NV; ++q)
-#pragma unroll
-                for (int d = 0; d < D; ++d) out[(size_t)(NV + q * D + d) * nf] = gx[q][d];
-            if (nbr[s] < 0) {
-                double Wg[NV], gg[NV][D];
-                ghost_state<D, true>(kp, tag[s], Wx, gx, nout[s], Wg, gg);
-                double* og = f.gpst + (size_t)((1 * NG + k) * NC) * nf + fid[s];
-#pragma unroll
-                for (int q = 0; q < NV; ++q) og[(size_t)q * nf] = Wg[q];
-#pragma unroll
-                for (int q = 0; q < NV; ++q)
-#pragma unroll
-                    for (int d = 0; d < D; ++d) og[(size_t)(NV + q * D + d) * nf] = gg[q][d];
-            }
-        }
+            for (int d = 0; d < D; ++d) og[(size_t)(NV + q * D + d) * nf] = gg[q][d];
+    }
 }
 
 template <int D>
@@ -330,21 +324,31 @@ __global__ void __launch_bounds__(BLOCK) k_flux(FineDev f, KParams kp0) {
     const int k = t / nf, fc = t - k * nf;
     const KParams kp = localize(kp0, f.ptab, f.fpid, fc);
     double WL[NV], WR[NV], gL[NV][D], gR[NV][D], nn[D];
-    const double* sL = f.gpst + (size_t)((0 * NG + k) * NC) * nf + fc;
-    const double* sR = f.gpst + (size_t)((1 * NG + k) * NC) * nf + fc;
+    constexpr int NS = S::NS;
+    const int L = f.fL[fc], R = f.fR[fc], sl = f.fslot[fc];
+    const size_t cs = (size_t)f.n * NS;
+    const double* sL = f.gps + ((size_t)(k * NC) * f.n + L) * NS + (sl & 7);
+    const double* sR;
+    size_t rs;
+    if (R >= 0) {
+        sR = f.gps + ((size_t)(k * NC) * f.n + R) * NS + (sl >> 3);
+        rs = cs;
+    } else {
+        sR = f.gho + (size_t)(k * NC) * nf + fc;
+        rs = nf;
+    }
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        WL[q] = sL[(size_t)q * nf];
-        WR[q] = sR[(size_t)q * nf];
+        WL[q] = sL[q * cs];
+        WR[q] = sR[q * rs];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            gL[q][d] = sL[(size_t)(NV + q * D + d) * nf];
-            gR[q][d] = sR[(size_t)(NV + q * D + d) * nf];
+            gL[q][d] = sL[(NV + q * D + d) * cs];
+            gR[q][d] = sR[(NV + q * D + d) * rs];
         }
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) nn[d] = f.fn[d * nf + fc];
-    const int L = f.fL[fc], R = f.fR[fc];
     double dt = f.dt[L];
     if (R >= 0) dt = fmin(dt, f.dt[R]);
     double F[NV], G[NV], a;
@@ -434,7 +438,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
             const double sg = (sf & 1) ? -1.0 : 1.0;
             double nn[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) nn[d] = sg * f.fn[d * nf + fc];
+            for (int d = 0; d < D; ++d) nn[d] = f.slot_n[(d * NS + s) * n + i];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 double fs = 0.0, gs = 0.0;
@@ -540,7 +544,7 @@ __global__ void k_count(int* counter) {
 /* ----------------------------------------------------------------- coarse --- */
 
 template <int D, class T>
-__global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp0, int mode) {
+__global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0, int mode, int hi1) {
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
@@ -611,8 +615,130 @@ __global__ void __launch_bounds__(BLOCK) k_coarse_rhs(CoarseDev c, KParams kp0, 
 #pragma unroll
     for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = Res[q] + c.F[q * n + I];
     const double a = kp.df_relax ? c.alpha[I] : 1.0;
-    c.D[I] = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+    const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+    c.D[I] = Dd;
+    /* The forward sweep of the first colour has no lower neighbours: its
+     * correction is rhs / D, formed here exactly as the sweep would. */
+    if (I < hi1) {
+        T* dW = reinterpret_cast<T*>(c.dW);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dW[q * n + I] = (T)(Res[q] + c.F[q * n + I]) / (T)Dd;
+    }
 }
+
+/* Coarse right-hand side with one thread per (cell, face slot): block
+ * (CELLS, nslot), slot terms combined in slot order by the slot-0 thread.
+ * Same arithmetic as one thread per cell, with nslot times the parallelism
+ * (the coarse levels are too small to fill the chip one cell per thread). */
+constexpr int MAXS = 8;     /* most face slots handled by the slot-parallel kernels */
+constexpr int SCELLS = 64;  /* cells per block of the slot-parallel kernels */
+template <int D, class T>
+__global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KParams kp0, int mode, int hi1) {
+    constexpr int NV = D + 2;
+    constexpr int NX = NV + 3;                 /* S F[q], S r, S (|u.n| + c), S^2 */
+    __shared__ double part[NX][MAXS][SCELLS];
+    const int tx = threadIdx.x, s = threadIdx.y;
+    const int I = blockIdx.x * SCELLS + tx;
+    const int n = c.n;
+    const bool live = I < n;
+    const KParams kp = localize(kp0, c.ptab, c.pid, live ? I : 0);
+    double W[NV];
+    Prim P;
+    double cs = 0.0;
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) W[q] = c.W[q * n + I];
+        primitive<D>(kp, W, P);
+        cs = sqrt(kp.gamma * P.p / P.rho);
+    }
+    const double visc = fmax(4.0 / 3.0, kp.gamma / kp.prandtl);
+    double x[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) x[k] = 0.0;
+    if (live) {
+        const int J = c.snbr[s * n + I];
+        const int tg = c.stag[s * n + I];
+        if (J >= 0 || tg != 0) {
+            const double S = c.sS[s * n + I];
+            double nn[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) nn[d] = c.sn[(d * c.nslot + s) * n + I];
+            double WJ[NV], F[NV], Wm[NV];
+            if (J >= 0) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    WJ[q] = c.W[q * n + J];
+                    Wm[q] = 0.5 * (W[q] + WJ[q]);
+                }
+            } else {
+                ghost_state<D, false>(kp, tg, W, nullptr, nn, WJ, nullptr);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) Wm[q] = W[q];
+            }
+            const double dist = c.sd[s * n + I];
+            kfvs_flux<D>(kp, W, WJ, nn, F);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) x[q] = S * F[q];
+            Prim Pm;
+            primitive<D>(kp, Wm, Pm);
+            double umn = 0.0, un = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                umn += Pm.U[d] * nn[d];
+                un += P.U[d] * nn[d];
+            }
+            double r = kp.omega * (fabs(umn) + sqrt(kp.gamma * Pm.p / Pm.rho));
+            if (kp.reynolds > 0.0) r += 2.0 * visc * sutherland(kp, Pm.p / Pm.rho) / (Pm.rho * dist);
+            reinterpret_cast<T*>(c.r)[s * n + I] = (T)r;
+            x[NV] = S * r;
+            x[NV + 1] = S * (fabs(un) + cs);
+            x[NV + 2] = S * S;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) part[k][s][tx] = x[k];
+    __syncthreads();
+    if (s != 0 || !live) return;
+    double Res[NV], sr = 0.0, lam = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Res[q] = 0.0;
+    for (int k = 0; k < c.nslot; ++k) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Res[q] -= part[q][k][tx];
+        sr += part[NV][k][tx];
+        lam += part[NV + 1][k][tx];
+        s2 += part[NV + 2][k][tx];
+    }
+    if (mode == COARSE_FORCING) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) c.F[q * n + I] = (double)reinterpret_cast<const T*>(c.Rstar)[q * n + I] - Res[q];
+        return;
+    }
+    if (kp.reynolds > 0.0) lam += visc * sutherland(kp, P.p / P.rho) / P.rho * s2 / c.V[I];
+    const double V = c.V[I];
+    const double dte = kp.cfl_exp * V / lam, dti = kp.cfl_imp * V / lam;
+    c.dte[I] = dte;
+    c.dti[I] = dti;
+    double rhs[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        rhs[q] = Res[q] + c.F[q * n + I];
+        c.rhs[q * n + I] = rhs[q];
+    }
+    const double a = kp.df_relax ? c.alpha[I] : 1.0;
+    const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+    c.D[I] = Dd;
+    if (I < hi1) {
+        T* dW = reinterpret_cast<T*>(c.dW);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dW[q * n + I] = (T)rhs[q] / (T)Dd;
+    }
+}
+
+/* One colour of an LU-SGS sweep with one thread per (cell, face slot); the
+ * slot-0 thread combines the neighbour terms in slot order and updates dW. */
+template <int D, class T>
+__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd);
 
 /* Increment of the normal Euler flux T(W + dW) - T(W).  In FP64 it is the
  * literal difference; in FP32 it is written in terms of the increments so no
@@ -664,7 +790,7 @@ __device__ __forceinline__ void flux_increment(const KParams& kp, const double* 
  * below lo and higher colours at or above hi.  T is the type of the
  * correction arithmetic: double (FP64) or float (mixed precision). */
 template <int D, class T>
-__global__ void __launch_bounds__(BLOCK) k_lusgs(CoarseDev c, KParams kp, int lo, int hi, int fwd) {
+__global__ void __launch_bounds__(CBLOCK) k_lusgs(CoarseDev c, KParams kp, int lo, int hi, int fwd) {
     constexpr int NV = D + 2;
     const int I = lo + blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
@@ -703,10 +829,61 @@ __global__ void __launch_bounds__(BLOCK) k_lusgs(CoarseDev c, KParams kp, int lo
     }
 }
 
+template <int D, class T>
+__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd) {
+    constexpr int NV = D + 2;
+    __shared__ T part[NV][MAXS][SCELLS];
+    const int tx = threadIdx.x, s = threadIdx.y;
+    const int I = lo + blockIdx.x * SCELLS + tx;
+    const int n = c.n;
+    const bool live = I < hi;
+    T* dW = reinterpret_cast<T*>(c.dW);
+    T x[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) x[q] = 0;
+    if (live) {
+        const int J = c.snbr[s * n + I];
+        if (J >= 0 && (fwd ? (J < lo) : (J >= hi))) {
+            const T S = (T)c.sS[s * n + I], r = reinterpret_cast<const T*>(c.r)[s * n + I];
+            T nn[D], dJ[NV], dT[NV];
+            double WJ[NV];
+#pragma unroll
+            for (int d = 0; d < D; ++d) nn[d] = (T)c.sn[(d * c.nslot + s) * n + I];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                WJ[q] = c.W[q * n + J];
+                dJ[q] = dW[q * n + J];
+            }
+            flux_increment<D, T>(kp, WJ, dJ, nn, dT);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) x[q] = S * (dT[q] - r * dJ[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) part[q][s][tx] = x[q];
+    __syncthreads();
+    if (s != 0 || !live) return;
+    T acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0;
+    for (int k = 0; k < c.nslot; ++k)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += part[q][k][tx];
+    const T a = kp.df_relax ? (T)c.alpha[I] : (T)1;
+    const T Di = (T)c.D[I];
+    if (fwd) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dW[q * n + I] = ((T)c.rhs[q * n + I] - (T)0.5 * a * acc[q]) / Di;
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) dW[q * n + I] -= (T)0.5 * a * acc[q] / Di;
+    }
+}
+
 /* Restriction (Sec. 5.2): W0 = sum V W / V_c (FP64), Res* = sum Res (in T),
  * alpha = min. */
 template <int D, class T>
-__global__ void __launch_bounds__(BLOCK) k_restrict(CoarseDev c, const double* Wf, const double* Vf,
+__global__ void __launch_bounds__(CBLOCK) k_restrict(CoarseDev c, const double* Wf, const double* Vf,
                                                    const double* resf, const double* af, int nfine) {
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -745,7 +922,7 @@ __global__ void __launch_bounds__(BLOCK) k_restrict(CoarseDev c, const double* W
  * alpha (W - W0) is formed in T and applied through update_fraction; cells
  * that apply less than all of it are counted. */
 template <int D, class T>
-__global__ void __launch_bounds__(BLOCK) k_prolong(CoarseDev c, double* Wf, const double* af, int nfine,
+__global__ void __launch_bounds__(CBLOCK) k_prolong(CoarseDev c, double* Wf, const double* af, int nfine,
                                                   int df, double kappa, unsigned long long* skips) {
     constexpr int NV = D + 2;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -770,7 +947,7 @@ __global__ void __launch_bounds__(BLOCK) k_prolong(CoarseDev c, double* Wf, cons
 
 /* Coarse LU-SGS update W += theta dW per cell (dW in T). */
 template <int D, class T>
-__global__ void __launch_bounds__(BLOCK) k_coarse_add(double* Wc, const double* dWraw, int n, double kappa) {
+__global__ void __launch_bounds__(CBLOCK) k_coarse_add(double* Wc, const double* dWraw, int n, double kappa) {
     constexpr int NV = D + 2;
     const T* dWc = reinterpret_cast<const T*>(dWraw);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -799,6 +976,7 @@ __global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a, double* b
 /* ------------------------------------------------------------- launchers --- */
 
 static inline int nblk(long m) { return (int)((m + BLOCK - 1) / BLOCK); }
+static inline int cblk(long m) { return (int)((m + CBLOCK - 1) / CBLOCK); }
 
 static inline int blocks(long m, int b) { return (int)((m + b - 1) / b); }
 
@@ -807,8 +985,10 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
     FineDev& f = c->fine;
     hipStream_t st = c->stream;
     if (which == 0) {
-        const int b = block ? block : c->blk_recon;
-        k_recon<D><<<blocks(f.n, b), b, 0, st>>>(f, c->kp);
+        /* block = cells per block x faces x Gauss points */
+        using S = Shape<D>;
+        const int cells = std::min(block ? block : c->blk_recon, RMAXC);
+        k_recon2<D><<<blocks(f.n, cells), cells * S::NS * S::NG, 0, st>>>(f, c->kp, cells);
     } else if (which == 1) {
         const int b = block ? block : c->blk_flux;
         k_flux<D><<<blocks((long)f.nf * f.ngp, b), b, 0, st>>>(f, c->kp);
@@ -855,7 +1035,13 @@ void launch_fine_residual(cgks_ctx* c, int mode) {
 
 template <int D, class T>
 static void coarse_rhs(cgks_ctx* c, CoarseDev& L, int mode) {
-    k_coarse_rhs<D, T><<<nblk(L.n), BLOCK, 0, c->stream>>>(L, c->kp, mode);
+    const int hi1 = mode == COARSE_RHS && L.ncolor > 0 ? L.color_off[1] : 0;
+    if (L.nslot <= MAXS) {
+        const dim3 blk(SCELLS, L.nslot);
+        k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), blk, 0, c->stream>>>(L, c->kp, mode, hi1);
+    } else {
+        k_coarse_rhs<D, T><<<cblk(L.n), CBLOCK, 0, c->stream>>>(L, c->kp, mode, hi1);
+    }
 }
 
 void launch_coarse_rhs(cgks_ctx* c, int level, int mode) {
@@ -867,12 +1053,18 @@ void launch_coarse_rhs(cgks_ctx* c, int level, int mode) {
 
 template <int D, class T>
 static void lusgs(cgks_ctx* c, CoarseDev& L) {
+    /* The first colour's forward step is done by the right-hand-side kernel;
+     * the last colour's backward step has no higher neighbours (a no-op). */
     for (int pass = 0; pass < 2; ++pass)
-        for (int k = 0; k < L.ncolor; ++k) {
+        for (int k = 1; k < L.ncolor; ++k) {
             const int col = pass == 0 ? k : L.ncolor - 1 - k;
             const int lo = L.color_off[col], hi = L.color_off[col + 1];
             if (hi <= lo) continue;
-            k_lusgs<D, T><<<nblk(hi - lo), BLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
+            if (L.nslot <= MAXS)
+                k_lusgs_s<D, T><<<blocks(hi - lo, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
+                                                                                                   pass == 0);
+            else
+                k_lusgs<D, T><<<cblk(hi - lo), CBLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
         }
 }
 
@@ -886,14 +1078,14 @@ void launch_lusgs(cgks_ctx* c, int level) {
 void launch_coarse_update(cgks_ctx* c, int level) {
     CoarseDev& L = c->coarse[level - 1];
     const bool mx = c->p.precision == CGKS_MIXED;
-    const int nb = nblk(L.n);
+    const int nb = cblk(L.n);
     const double kap = c->kp.update_limit;
     if (c->dim == 2) {
-        if (mx) k_coarse_add<2, float><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
-        else k_coarse_add<2, double><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        if (mx) k_coarse_add<2, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        else k_coarse_add<2, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
     } else {
-        if (mx) k_coarse_add<3, float><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
-        else k_coarse_add<3, double><<<nb, BLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        if (mx) k_coarse_add<3, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        else k_coarse_add<3, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
     }
 }
 
@@ -908,13 +1100,13 @@ void launch_restrict(cgks_ctx* c, int level) {
         Wf = F.W; Vf = F.V; rf = F.rhs; af = F.alpha; nfine = F.n;
     }
     const bool mx = c->p.precision == CGKS_MIXED;
-    const int nb = nblk(G.n);
+    const int nb = cblk(G.n);
     if (c->dim == 2) {
-        if (mx) k_restrict<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
-        else k_restrict<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        if (mx) k_restrict<2, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        else k_restrict<2, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
     } else {
-        if (mx) k_restrict<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
-        else k_restrict<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        if (mx) k_restrict<3, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        else k_restrict<3, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
     }
 }
 
@@ -930,15 +1122,15 @@ void launch_prolong(cgks_ctx* c, int level) {
         Wf = F.W; af = F.alpha; nfine = F.n;
     }
     const bool mx = c->p.precision == CGKS_MIXED;
-    const int nb = nblk(nfine), df = c->kp.df_prolong;
+    const int nb = cblk(nfine), df = c->kp.df_prolong;
     const double kap = c->kp.update_limit;
     unsigned long long* sk = c->ws.skips;
     if (c->dim == 2) {
-        if (mx) k_prolong<2, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
-        else k_prolong<2, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        if (mx) k_prolong<2, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        else k_prolong<2, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
     } else {
-        if (mx) k_prolong<3, float><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
-        else k_prolong<3, double><<<nb, BLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        if (mx) k_prolong<3, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
+        else k_prolong<3, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, af, nfine, df, kap, sk);
     }
 }
 

@@ -518,8 +518,10 @@ __host__ __device__ __forceinline__ void ghost_state(const KParams& kp, int tag,
 #pragma unroll
             for (int d = 0; d < D; ++d) Ub[d] = U[d];
         } else {
+            /* subsonic: interior entropy and tangential velocity where the free
+             * stream leaves (u_inf . n > 0), free-stream ones elsewhere */
             double ent;
-            if (ub > 0.0) {
+            if (uinf_n > 0.0) {
                 ent = p / pow(rho, gm);
 #pragma unroll
                 for (int d = 0; d < D; ++d) Ub[d] = U[d] - un * n[d] + ub * n[d];

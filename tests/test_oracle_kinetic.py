@@ -281,6 +281,28 @@ def test_farfield_ghost_of_free_stream_is_free_stream(orc):
             np.testing.assert_allclose(Wg, Winf, rtol=1e-14, atol=1e-14)
 
 
+def test_farfield_subsonic_branch_follows_free_stream_direction(orc):
+    """Riemann invariants fix the boundary normal velocity and sound speed; the
+    entropy (and tangential velocity) come from the interior where the free stream
+    leaves through the face (u_inf . n > 0) and from the free stream elsewhere,
+    whatever the sign of the local normal velocity."""
+    G, mach = 1.4, 0.5
+    for ang, outflow in ((80.0, True), (100.0, False)):
+        n = np.array([np.cos(np.radians(ang)), np.sin(np.radians(ang))])
+        # interior: the free stream's sound speed but another entropy, moving against
+        # the free stream's normal direction
+        rho, p = 1.2, 1.2 / G
+        u = np.array([mach, 0.0]) - (0.2 if outflow else -0.2) * n
+        W = np.array([rho, rho * u[0], rho * u[1], p / (G - 1) + 0.5 * rho * u @ u])
+        Wg, _ = orc.ghost(1, W, None, n, mach=mach)
+        ub = 0.5 * ((u @ n + 2 * np.sqrt(G * p / rho) / (G - 1)) + (mach * n[0] - 2 * np.sqrt(G / G * 1.0) / (G - 1)))
+        assert (ub > 0) != outflow           # the local normal velocity points the other way
+        pg = (G - 1) * (Wg[3] - 0.5 * (Wg[1] ** 2 + Wg[2] ** 2) / Wg[0])
+        s_ghost, s_in, s_inf = pg / Wg[0] ** G, p / rho ** G, (1.0 / G)
+        assert s_ghost == pytest.approx(s_in if outflow else s_inf, rel=1e-12)
+        assert (Wg[1:3] / Wg[0]) @ n == pytest.approx(ub, rel=1e-12)
+
+
 def test_isothermal_ghost_sets_wall_temperature_and_no_slip(orc):
     W = cons(1.3, [0.2, -0.1], 0.9)
     n = np.array([0.0, -1.0])
