@@ -95,7 +95,9 @@ typedef struct cgks_params {
     double lusgs_omega;        /* spectral-radius safety factor r >= |U.n| + c (Sec. 4.2), default 1 */
     double skew_limit;         /* Alg. 3 minimum sin(skewness angle), default 0.2 */
     double slope_relax;        /* theta of the fine slope update grad <- grad + theta (grad_new - grad);
-                                  1 = full replacement (Sec. 2.4); same fixed point for any theta in (0,1] */
+                                  1 = full replacement (Sec. 2.4); same fixed point for any theta in
+                                  (0,1].  Default 0.3: with 1 the V-cycle stalls near 3e-4 on a steady
+                                  Re 40 cylinder, with 0.3 it converges to round-off */
     double update_limit;       /* kappa of the update safeguard of coarse LU-SGS updates and prolongation
                                   corrections: each cell applies the largest fraction 1, 1/2, ..., 2^-10
                                   (else 0) of its update that keeps rho and p positive and at least
@@ -215,10 +217,12 @@ int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double*
 int cgks_run_cycles(cgks_ctx* c, int n, double* history);
 
 /* Average duration in milliseconds of one kernel of the fine residual at the
- * current state, timed with HIP events on the context's stream over `reps`
- * back-to-back launches: kernel 0 = reconstruction (per cell), 1 = Gauss-point
- * flux (per face Gauss point), 2 = gather (per cell).  The state is not
- * modified.  Also returns the number of work items of one launch. */
+ * current state: kernel 0 = reconstruction (per cell), 1 = Gauss-point flux
+ * (per face Gauss point), 2 = gather (per cell).  Each of the `reps`
+ * repetitions runs the whole fine residual on the context's stream, with HIP
+ * events around the chosen kernel only, so the kernel sees the cache state of
+ * a V-cycle.  The state is not modified.  Also returns the number of work
+ * items of one launch. */
 int cgks_time_kernel(cgks_ctx* c, int kernel, int reps, double* avg_ms, int64_t* work_items);
 
 /* Choose the launch shape (threads per block) of each fine-residual kernel by

@@ -32,12 +32,12 @@ class Params(C.Structure):
     ]
 
 
-# The oracle's own defaults: the readings of the paper.
+# The oracle's own defaults: its readings of the paper where the paper is silent.
 DEFAULTS = dict(dim=2, gamma=1.4, prandtl=0.72, mach=0.38, aoa_deg=0.0, reynolds=0.0,
                 wall_T_ratio=1.0, sutherland_S_ratio=0.5, cfl_exp=0.5, cfl_imp=10.0,
                 n_levels=3, n_pre_fine=1, n_post=0, n_sweeps=6, df_relax=1, df_prolong=1,
                 precision=0, tau_c1=0.01, tau_c2=1.0, weno_gamma_large=0.95,
-                weno_eps=1e-14, lusgs_omega=1.0, skew_limit=0.2, slope_relax=1.0,
+                weno_eps=1e-14, lusgs_omega=1.0, skew_limit=0.2, slope_relax=0.3,
                 update_limit=0.5)
 
 

@@ -483,6 +483,10 @@ void ghost(const orc_params& p, int tag, const double* W, const double* g, const
             ke += Ub[d] * Ub[d];
         }
         Wg[nv - 1] = pb / (gm - 1.0) + 0.5 * rb * ke;
+        /* derivatives: those of the interior state (zero normal gradient of the
+         * derivatives across the boundary) */
+        if (gg && g)
+            for (int i = 0; i < nv * dim; ++i) gg[i] = g[i];
         return;
     }
     if (tag == TAG_SLIP) {

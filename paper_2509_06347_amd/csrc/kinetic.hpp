@@ -541,11 +541,12 @@ __host__ __device__ __forceinline__ void ghost_state(const KParams& kp, int tag,
             k2 += Ub[d] * Ub[d];
         }
         Wg[D + 1] = pb / (gm - 1.0) + 0.5 * rb * k2;
+        /* derivatives: those of the interior state */
         if constexpr (GRAD) {
 #pragma unroll
             for (int q = 0; q < NV; ++q)
 #pragma unroll
-                for (int d = 0; d < D; ++d) gg[q][d] = 0.0;
+                for (int d = 0; d < D; ++d) gg[q][d] = g[q][d];
         }
         return;
     }
