@@ -219,6 +219,97 @@ def draw_flow_params(seed, n, mach=(0.3, 8.0), log10_re=(3.0, 5.0)):
     return out
 
 
+_KUHN = ((0, 1, 3, 7), (0, 1, 5, 7), (0, 2, 3, 7), (0, 2, 6, 7), (0, 4, 5, 7), (0, 4, 6, 7))
+
+
+def _orient_tets(xyz, tets):
+    """Swap two nodes of every negatively oriented tetrahedron."""
+    a, b, c, d = (xyz[tets[:, k]] for k in range(4))
+    vol = np.einsum("ij,ij->i", np.cross(b - a, c - a), d - a)
+    neg = vol < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return tets
+
+
+def _refine_tet(xyz, tets):
+    """1 -> 8 refinement: four corner tetrahedra and the inner octahedron cut
+    along the diagonal joining the midpoints of edges 02 and 13.  Child c of
+    parent p is 8 p + c."""
+    mid = {}
+    pts = [p for p in xyz]
+
+    def midpoint(a, b):
+        key = (a, b) if a < b else (b, a)
+        if key not in mid:
+            mid[key] = len(pts)
+            pts.append(0.5 * (xyz[a] + xyz[b]))
+        return mid[key]
+
+    out = []
+    for t in tets:
+        p0, p1, p2, p3 = (int(x) for x in t)
+        m01, m02, m03 = midpoint(p0, p1), midpoint(p0, p2), midpoint(p0, p3)
+        m12, m13, m23 = midpoint(p1, p2), midpoint(p1, p3), midpoint(p2, p3)
+        out += [(p0, m01, m02, m03), (m01, p1, m12, m13), (m02, m12, p2, m23), (m03, m13, m23, p3),
+                (m02, m13, m01, m03), (m02, m13, m03, m23), (m02, m13, m23, m12), (m02, m13, m12, m01)]
+    xyz = np.array(pts)
+    return xyz, _orient_tets(xyz, np.array(out, dtype=np.int64))
+
+
+def box_tets(n, nref=2, jitter=0.0, seed=0, tags=None, size=1.0):
+    """Cube [0, size]^3 of n^3 hexahedra, each split into 6 tetrahedra along its
+    main diagonal (a conforming split), interior nodes jittered by +-jitter*h,
+    then refined 1 -> 8 nref times.  tags maps a side ('x0', 'x1', 'y0', 'y1',
+    'z0', 'z1') to its boundary tag (default far field)."""
+    rng = np.random.default_rng(seed)
+    side_tag = {k: FARFIELD for k in ("x0", "x1", "y0", "y1", "z0", "z1")}
+    side_tag.update(tags or {})
+    h = size / n
+    g = np.linspace(0.0, size, n + 1)
+    xyz = np.array([[x, y, z] for z in g for y in g for x in g], dtype=np.float64)
+    if jitter > 0.0:
+        for k in range(1, n):
+            for j in range(1, n):
+                for i in range(1, n):
+                    xyz[(k * (n + 1) + j) * (n + 1) + i] += jitter * h * rng.uniform(-1.0, 1.0, size=3)
+
+    def nid(i, j, k):
+        return (k * (n + 1) + j) * (n + 1) + i
+
+    tets = []
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                v = [nid(i + (c & 1), j + ((c >> 1) & 1), k + ((c >> 2) & 1)) for c in range(8)]
+                tets += [tuple(v[a] for a in t) for t in _KUHN]
+    tets = _orient_tets(xyz, np.array(tets, dtype=np.int64))
+    parents = []
+    for _ in range(nref):
+        xyz, tets = _refine_tet(xyz, tets)
+        parents.insert(0, np.arange(len(tets), dtype=np.int32) // 8)
+    # boundary faces: faces used by exactly one tetrahedron
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    key = np.sort(faces, axis=1)
+    _, first, count = np.unique(key, axis=0, return_index=True, return_counts=True)
+    bf = faces[first[count == 1]]
+    btags = []
+    tol = 1e-12 * size
+    for f in bf:
+        c = xyz[f]
+        for d, ax in enumerate("xyz"):
+            if np.all(np.abs(c[:, d]) < tol):
+                btags.append(side_tag[ax + "0"])
+                break
+            if np.all(np.abs(c[:, d] - size) < tol):
+                btags.append(side_tag[ax + "1"])
+                break
+        else:
+            raise ValueError("boundary face off the box")
+    return Mesh(3, np.ascontiguousarray(xyz), np.ascontiguousarray(tets, dtype=np.int32),
+                np.ascontiguousarray(bf, dtype=np.int32), np.array(btags, dtype=np.int32), parents,
+                dict(kind="box_tets", n=n, nref=nref, jitter=jitter, seed=seed))
+
+
 # Named workloads ----------------------------------------------------------
 
 def cylinder_euler_small(seed=0):
