@@ -259,3 +259,111 @@ def test_lusgs_update_limit_bounds_the_drop(orc, small_mesh, scale):
     assert np.all(W1[:, 0] >= 0.5 * W[:, 0])
     assert np.all(_rho_e(W1) >= 0.5 * _rho_e(W))
     assert np.abs(W1 - W).max() > 0
+
+
+# ---- 3-D (tetrahedra) ------------------------------------------------------
+
+def _tet_mesh(**kw):
+    return sm.box_tets(2, nref=1, jitter=0.1, seed=kw.pop("seed", 6), **kw)
+
+
+def cons_field_3d(C, mach=0.5, amp=0.05):
+    x, y, z = C[:, 0], C[:, 1], C[:, 2]
+    rho = 1.0 + amp * np.sin(2.0 * x + 0.3) * np.cos(1.5 * y - z)
+    u = mach * (1.0 + amp * np.cos(2.0 * z))
+    v = mach * amp * np.sin(1.7 * x)
+    w = mach * amp * np.cos(2.1 * y)
+    p = 1.0 / G * (1.0 + amp * np.cos(1.3 * x - 0.7 * y + z))
+    return np.stack([rho, rho * u, rho * v, rho * w, p / (G - 1) + 0.5 * rho * (u * u + v * v + w * w)], axis=-1)
+
+
+def test_free_stream_preservation_3d(orc):
+    m = _tet_mesh()
+    o = orc.Oracle(m, n_levels=2, dim=3, mach=0.7, aoa_deg=10.0)
+    o.init_freestream()
+    W0, _, _ = o.get_state()
+    R, g, a = o.residual(0)
+    assert np.abs(R).max() <= 1e-15 and np.abs(g).max() <= 1e-12 and (a == 1.0).all()
+    o.vcycle()
+    assert np.abs(o.get_state()[0] - W0).max() <= 1e-13
+
+
+def test_closed_box_conserves_mass_and_energy_3d(orc):
+    m = _tet_mesh(tags={k: sm.SLIP for k in ("x0", "x1", "y0", "y1", "z0", "z1")})
+    for re in (0.0, 200.0):
+        o = orc.Oracle(m, n_levels=1, dim=3, mach=0.5, reynolds=re)
+        V, C = o.cell_geometry(0)
+        o.set_state(cons_field_3d(C))
+        R, _, _ = o.residual(0)
+        for q in (0, 4):
+            assert abs(R[:, q].sum()) <= 1e-14 * np.abs(R[:, q]).sum() + 1e-16
+
+
+def _tet_avg_quadratic(P, c):
+    """Exact average over tetrahedra of c0 + sum_a c_a x_a + sum_{a<=b} c_ab x_a x_b:
+    the mean of x_a x_b is (sum_i x_ia x_ib + (sum_i x_ia)(sum_i x_ib)) / 20."""
+    s = P.sum(axis=1)
+    out = c[0] + sum(c[1 + a] * s[:, a] / 4 for a in range(3))
+    k = 4
+    for a in range(3):
+        for b in range(a, 3):
+            out = out + c[k] * ((P[:, :, a] * P[:, :, b]).sum(axis=1) + s[:, a] * s[:, b]) / 20
+            k += 1
+    return out
+
+
+def _quad3(c, x):
+    v = c[0] + sum(c[1 + a] * x[a] for a in range(3))
+    k = 4
+    for a in range(3):
+        for b in range(a, 3):
+            v += c[k] * x[a] * x[b]
+            k += 1
+    return v
+
+
+def _quad3_grad(c, x):
+    g = np.array([c[1], c[2], c[3]], dtype=float)
+    k = 4
+    for a in range(3):
+        for b in range(a, 3):
+            g[a] += c[k] * x[b]
+            g[b] += c[k] * x[a]
+            k += 1
+    return g
+
+
+def test_large_stencil_reproduces_quadratics_3d(orc):
+    """On tetrahedra, p^2 (9 terms) fits 4 neighbour averages exactly and 12 slope
+    rows in the least-squares sense: quadratic data are reproduced exactly."""
+    m = _tet_mesh(seed=8)
+    o = orc.Oracle(m, n_levels=1, dim=3, mach=0.3)
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(1)
+    coefs = [rng.normal(scale=[1.0] + [0.05] * 3 + [0.02] * 6) for _ in range(5)]
+    coefs[0][0] = 1.0
+    coefs[4][0] = 2.5
+    P = m.coords[m.cells]
+    W = np.stack([_tet_avg_quadratic(P, c) for c in coefs], axis=1)
+    grad = np.stack([np.array([_quad3_grad(c, x) for x in C]) for c in coefs], axis=1)
+    o.set_state(W, grad)
+    fg = o.face_geometry(0)
+    interior = np.bincount(fg["LR"][fg["LR"][:, 1] >= 0].ravel(), minlength=m.n_cells)
+    for i in rng.choice(np.where(interior == 4)[0], 15, replace=False):
+        for x in (C[i], P[i, 0] * 0.6 + 0.4 * C[i], P[i, 3]):
+            _, _, p2, _, _ = o.recon_eval(int(i), x)
+            np.testing.assert_allclose(p2, [_quad3(c, x) for c in coefs], rtol=0, atol=1e-11)
+
+
+def test_multicolour_lusgs_equals_sequential_lusgs_3d(orc):
+    m = sm.box_tets(2, nref=2, jitter=0.1, seed=3, tags={"z0": sm.SLIP})
+    runs = []
+    for seq in (False, True):
+        o = orc.Oracle(m, n_levels=3, dim=3, mach=0.5)
+        V, C = o.cell_geometry(0)
+        o.set_state(cons_field_3d(C))
+        o.smooth(0, 1)
+        o.restrict(0)
+        (o.smooth_sequential if seq else o.smooth)(1, 2)
+        runs.append(o.get_level_state(1)[0])
+    assert np.array_equal(runs[0], runs[1])
