@@ -156,12 +156,6 @@ void enqueue_restrict(cgks_ctx* c, int l) {
     launch_coarse_rhs(c, l + 1, COARSE_FORCING);
 }
 
-void enqueue_lusgs_iter(cgks_ctx* c, int l) {
-    launch_coarse_rhs(c, l, COARSE_RHS);
-    launch_lusgs(c, l);
-    launch_coarse_update(c, l);
-}
-
 /* One V-cycle: fine pre-smoothing, restriction, coarse LU-SGS, prolongation. */
 void enqueue_vcycle(cgks_ctx* c) {
     const int nl = (int)c->hl.size();
@@ -169,7 +163,7 @@ void enqueue_vcycle(cgks_ctx* c) {
     for (int s = 0; s < c->p.n_pre_fine; ++s) launch_fine_residual(c, s == 0 ? FINE_STEP_NORM : FINE_STEP);
     for (int l = 0; l + 1 < nl; ++l) {
         enqueue_restrict(c, l);
-        for (int s = 0; s < c->p.n_sweeps; ++s) enqueue_lusgs_iter(c, l + 1);
+        launch_lusgs_iters(c, l + 1, c->p.n_sweeps);
     }
     for (int l = nl - 2; l >= 0; --l) launch_prolong(c, l);
 }
@@ -393,7 +387,7 @@ int upload(cgks_ctx* c) {
         TRY(dalloc(c, &D.sS, (size_t)S * m)); TRY(h2d(c, D.sS, sS));
         TRY(dalloc(c, &D.sn, (size_t)dim * S * m)); TRY(h2d(c, D.sn, sn));
         TRY(dalloc(c, &D.sd, (size_t)S * m)); TRY(h2d(c, D.sd, sd));
-        for (double** p : {&D.W, &D.W0, &D.F, &D.Rstar, &D.dW, &D.rhs}) TRY(dalloc(c, p, (size_t)nv * m));
+        for (double** p : {&D.W, &D.Wb, &D.W0, &D.F, &D.Rstar, &D.dW, &D.rhs}) TRY(dalloc(c, p, (size_t)nv * m));
         for (double** p : {&D.alpha, &D.D, &D.dte, &D.dti}) TRY(dalloc(c, p, m));
         TRY(dalloc(c, &D.r, (size_t)S * m));
         TRY(dalloc(c, &D.parent, nfine)); TRY(h2d(c, D.parent, par));
@@ -696,11 +690,10 @@ int cgks_time_steps(cgks_ctx* c, int level, double* dt_exp, double* dt_imp) {
 
 int cgks_smooth(cgks_ctx* c, int level, int n) {
     TRY(check_level(c, level));
-    for (int s = 0; s < n; ++s) {
-        if (level == 0)
-            launch_fine_residual(c, FINE_STEP);
-        else
-            enqueue_lusgs_iter(c, level);
+    if (level == 0) {
+        for (int s = 0; s < n; ++s) launch_fine_residual(c, FINE_STEP);
+    } else if (n > 0) {
+        launch_lusgs_iters(c, level, n);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));

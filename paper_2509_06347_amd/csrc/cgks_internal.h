@@ -83,6 +83,7 @@ struct CoarseDev {
     int *snbr, *stag;                 /* [nslot][n] (internal neighbour, -1 boundary / empty) */
     double *sS, *sn, *sd;             /* [nslot][n], [dim][nslot][n], [nslot][n] viscous distance */
     double *W, *W0, *F, *Rstar, *alpha, *dW, *rhs, *D, *r, *dte, *dti;
+    double *Wb;                       /* second state buffer: LU-SGS iterations alternate W and Wb */
     int *parent;                      /* of the finer level's internal cells: this level's internal index */
     int *child_off, *child;           /* CSR of finer internal indices */
     const int* pid;                   /* batched solves: problem id per cell (else null) */
@@ -161,6 +162,8 @@ void launch_prolong(cgks_ctx* c, int level);
 void launch_norm_finalize(cgks_ctx* c);
 void launch_save_state(cgks_ctx* c);
 void launch_coarse_update(cgks_ctx* c, int level);
+/* n LU-SGS iterations on a coarse level (right-hand side, sweeps, update) */
+void launch_lusgs_iters(cgks_ctx* c, int level, int n);
 
 /* modes of launch_fine_residual */
 enum { FINE_EVAL = 0, FINE_STEP = 1, FINE_STEP_NORM = 2, FINE_RESTRICT = 3 };

@@ -633,7 +633,8 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
 constexpr int MAXS = 8;     /* most face slots handled by the slot-parallel kernels */
 constexpr int SCELLS = 64;  /* cells per block of the slot-parallel kernels */
 template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KParams kp0, int mode, int hi1) {
+__global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KParams kp0, int mode, int hi1,
+                                                                double* Wout1) {
     constexpr int NV = D + 2;
     constexpr int NX = NV + 3;                 /* S F[q], S r, S (|u.n| + c), S^2 */
     __shared__ double part[NX][MAXS][SCELLS];
@@ -730,15 +731,27 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
     c.D[I] = Dd;
     if (I < hi1) {
         T* dW = reinterpret_cast<T*>(c.dW);
+        double dWd[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dW[q * n + I] = (T)rhs[q] / (T)Dd;
+        for (int q = 0; q < NV; ++q) {
+            const T d = (T)rhs[q] / (T)Dd;
+            dW[q * n + I] = d;
+            dWd[q] = (double)d;
+        }
+        /* a single colour: this is the final correction; write the new state */
+        if (Wout1) {
+            const double th = update_fraction<D>(W, dWd, kp.update_limit);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Wout1[q * n + I] = th > 0.0 ? W[q] + th * dWd[q] : W[q];
+        }
     }
 }
 
 /* One colour of an LU-SGS sweep with one thread per (cell, face slot); the
  * slot-0 thread combines the neighbour terms in slot order and updates dW. */
 template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd);
+__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
+                                                           double* Wout);
 
 /* Increment of the normal Euler flux T(W + dW) - T(W).  In FP64 it is the
  * literal difference; in FP32 it is written in terms of the increments so no
@@ -830,7 +843,8 @@ __global__ void __launch_bounds__(CBLOCK) k_lusgs(CoarseDev c, KParams kp, int l
 }
 
 template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd) {
+__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
+                                                           double* Wout) {
     constexpr int NV = D + 2;
     __shared__ T part[NV][MAXS][SCELLS];
     const int tx = threadIdx.x, s = threadIdx.y;
@@ -871,12 +885,30 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams 
         for (int q = 0; q < NV; ++q) acc[q] += part[q][k][tx];
     const T a = kp.df_relax ? (T)c.alpha[I] : (T)1;
     const T Di = (T)c.D[I];
+    double dWd[NV];
     if (fwd) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dW[q * n + I] = ((T)c.rhs[q * n + I] - (T)0.5 * a * acc[q]) / Di;
+        for (int q = 0; q < NV; ++q) {
+            const T d = ((T)c.rhs[q * n + I] - (T)0.5 * a * acc[q]) / Di;
+            dW[q * n + I] = d;
+            dWd[q] = (double)d;
+        }
     } else {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dW[q * n + I] -= (T)0.5 * a * acc[q] / Di;
+        for (int q = 0; q < NV; ++q) {
+            const T d = dW[q * n + I] - (T)0.5 * a * acc[q] / Di;
+            dW[q * n + I] = d;
+            dWd[q] = (double)d;
+        }
+    }
+    /* the cell's correction is final: write its new state into the other buffer */
+    if (Wout) {
+        double W[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) W[q] = c.W[q * n + I];
+        const double th = update_fraction<D>(W, dWd, kp.update_limit);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Wout[q * n + I] = th > 0.0 ? W[q] + th * dWd[q] : W[q];
     }
 }
 
@@ -965,12 +997,15 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_add(double* Wc, const double*
     }
 }
 
-/* Copy the fine state to the roll-back buffers while no non-physical state
- * has been flagged. */
-__global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a, double* b, int m, const int* status) {
+/* Copy the fine state, slopes and DF (three arrays, one launch) to the
+ * roll-back buffers while no non-physical state has been flagged. */
+__global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a0, double* b0, int m0, const double* a1, double* b1,
+                                                      int m1, const double* a2, double* b2, int m2, const int* status) {
     if (*status) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < m) b[t] = a[t];
+    if (t < m0) b0[t] = a0[t];
+    else if (t < m0 + m1) b1[t - m0] = a1[t - m0];
+    else if (t < m0 + m1 + m2) b2[t - m0 - m1] = a2[t - m0 - m1];
 }
 
 /* ------------------------------------------------------------- launchers --- */
@@ -1038,7 +1073,7 @@ static void coarse_rhs(cgks_ctx* c, CoarseDev& L, int mode) {
     const int hi1 = mode == COARSE_RHS && L.ncolor > 0 ? L.color_off[1] : 0;
     if (L.nslot <= MAXS) {
         const dim3 blk(SCELLS, L.nslot);
-        k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), blk, 0, c->stream>>>(L, c->kp, mode, hi1);
+        k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), blk, 0, c->stream>>>(L, c->kp, mode, hi1, nullptr);
     } else {
         k_coarse_rhs<D, T><<<cblk(L.n), CBLOCK, 0, c->stream>>>(L, c->kp, mode, hi1);
     }
@@ -1062,7 +1097,7 @@ static void lusgs(cgks_ctx* c, CoarseDev& L) {
             if (hi <= lo) continue;
             if (L.nslot <= MAXS)
                 k_lusgs_s<D, T><<<blocks(hi - lo, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
-                                                                                                   pass == 0);
+                                                                                                   pass == 0, nullptr);
             else
                 k_lusgs<D, T><<<cblk(hi - lo), CBLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
         }
@@ -1073,6 +1108,50 @@ void launch_lusgs(cgks_ctx* c, int level) {
     const bool mx = c->p.precision == CGKS_MIXED;
     if (c->dim == 2) mx ? lusgs<2, float>(c, L) : lusgs<2, double>(c, L);
     else mx ? lusgs<3, float>(c, L) : lusgs<3, double>(c, L);
+}
+
+/* One LU-SGS iteration that reads the state from L.W and writes the new state
+ * to Wout: the last colour's forward step and every other colour's backward
+ * step write their cells' W + theta dW (the update safeguard) as soon as the
+ * correction is final; nothing in the iteration reads Wout. */
+template <int D, class T>
+static void lusgs_iter_pingpong(cgks_ctx* c, const CoarseDev& L, double* Wout) {
+    const int C = L.ncolor;
+    const int hi1 = C > 0 ? L.color_off[1] : 0;
+    k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, COARSE_RHS, hi1,
+                                                                                      C == 1 ? Wout : nullptr);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 1; k < C; ++k) {
+            const int col = pass == 0 ? k : C - 1 - k;
+            const int lo = L.color_off[col], hi = L.color_off[col + 1];
+            if (hi <= lo) continue;
+            double* w = (pass == 1 || col == C - 1) ? Wout : nullptr;
+            k_lusgs_s<D, T><<<blocks(hi - lo, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
+                                                                                               pass == 0, w);
+        }
+}
+
+void launch_lusgs_iters(cgks_ctx* c, int level, int n) {
+    CoarseDev& L = c->coarse[level - 1];
+    if (L.nslot > MAXS || L.ncolor < 1) {
+        for (int s = 0; s < n; ++s) {
+            launch_coarse_rhs(c, level, COARSE_RHS);
+            launch_lusgs(c, level);
+            launch_coarse_update(c, level);
+        }
+        return;
+    }
+    const bool mx = c->p.precision == CGKS_MIXED;
+    double* buf[2] = {L.W, L.Wb};
+    for (int s = 0; s < n; ++s) {
+        CoarseDev Ls = L;
+        Ls.W = buf[s & 1];
+        double* out = buf[(s + 1) & 1];
+        if (c->dim == 2) mx ? lusgs_iter_pingpong<2, float>(c, Ls, out) : lusgs_iter_pingpong<2, double>(c, Ls, out);
+        else mx ? lusgs_iter_pingpong<3, float>(c, Ls, out) : lusgs_iter_pingpong<3, double>(c, Ls, out);
+    }
+    if (n & 1)
+        (void)hipMemcpyAsync(L.W, L.Wb, (size_t)L.n * c->nv * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 }
 
 void launch_coarse_update(cgks_ctx* c, int level) {
@@ -1137,9 +1216,9 @@ void launch_prolong(cgks_ctx* c, int level) {
 void launch_save_state(cgks_ctx* c) {
     FineDev& f = c->fine;
     const int nv = c->nv, dim = c->dim;
-    k_save_if_ok<<<nblk((long)f.n * nv), BLOCK, 0, c->stream>>>(f.W, f.Wsave, f.n * nv, c->ws.status);
-    k_save_if_ok<<<nblk((long)f.n * nv * dim), BLOCK, 0, c->stream>>>(f.grad, f.gsave, f.n * nv * dim, c->ws.status);
-    k_save_if_ok<<<nblk(f.n), BLOCK, 0, c->stream>>>(f.alpha, f.asave, f.n, c->ws.status);
+    const int m0 = f.n * nv, m1 = f.n * nv * dim, m2 = f.n;
+    k_save_if_ok<<<nblk((long)m0 + m1 + m2), BLOCK, 0, c->stream>>>(f.W, f.Wsave, m0, f.grad, f.gsave, m1, f.alpha,
+                                                                    f.asave, m2, c->ws.status);
 }
 
 }  // namespace cgks
