@@ -1,0 +1,128 @@
+"""Failure handling through the C ABI (host-forced conditions; every kernel
+still exits normally): non-physical states, invalid meshes and parameters,
+mismatched batches, empty and degenerate inputs."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synthmesh as sm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2509_06347_amd import cgks
+    return cgks
+
+
+def _mesh():
+    return sm.annulus(12, 4, jitter=0.1, seed=3, nref=2, wall_tag=sm.SLIP)
+
+
+@pytest.mark.parametrize("what", ["nan", "negative_pressure"])
+def test_non_physical_state_is_reported_and_rolled_back(cg, what):
+    g = cg.Solver(_mesh(), n_levels=3, mach=0.5)
+    g.init_freestream()
+    g.run_cycles(2)
+    W, grad, a = g.get_state()
+    bad = W.copy()
+    if what == "nan":
+        bad[7, 1] = np.nan
+    else:
+        bad[7, 3] = 0.5 * (bad[7, 1] ** 2 + bad[7, 2] ** 2) / bad[7, 0] - 1.0   # rho e < 0
+    g.set_state(bad, grad, a)
+    with pytest.raises(cg.CgksError) as e:
+        g.run_cycles(3)
+    assert e.value.code == cg.ENONPHYS
+    # the state is the one at the start of the failing cycle (here: the injected one)
+    W2, _, _ = g.get_state()
+    np.testing.assert_array_equal(np.isnan(W2), np.isnan(bad))
+    np.testing.assert_array_equal(np.nan_to_num(W2), np.nan_to_num(bad))
+    # the context stays usable: a good state runs again
+    g.set_state(W, grad, a)
+    assert np.all(np.isfinite(g.run_cycles(2)))
+
+
+def test_inverted_cell_is_rejected(cg):
+    m = _mesh()
+    cells = m.cells.copy()
+    cells[5, [1, 2]] = cells[5, [2, 1]]
+    bad = dataclasses.replace(m, cells=cells)
+    with pytest.raises(cg.CgksError) as e:
+        cg.Solver(bad, n_levels=3, mach=0.5)
+    assert e.value.code == cg.EMESH
+
+
+def test_untagged_boundary_face_is_rejected(cg):
+    m = _mesh()
+    bad = dataclasses.replace(m, bfaces=m.bfaces[1:], btags=m.btags[1:])
+    with pytest.raises(cg.CgksError) as e:
+        cg.Solver(bad, n_levels=3, mach=0.5)
+    assert e.value.code == cg.EMESH
+
+
+def test_out_of_range_node_is_rejected(cg):
+    m = _mesh()
+    cells = m.cells.copy()
+    cells[0, 0] = m.n_nodes
+    with pytest.raises(cg.CgksError) as e:
+        cg.Solver(dataclasses.replace(m, cells=cells), n_levels=3, mach=0.5)
+    assert e.value.code == cg.EMESH
+
+
+@pytest.mark.parametrize("bad", [dict(slope_relax=0.0), dict(slope_relax=1.5), dict(update_limit=1.5),
+                                 dict(precision=7), dict(mach=0.0), dict(n_post=1)])
+def test_invalid_parameters_are_rejected(cg, bad):
+    with pytest.raises(cg.CgksError) as e:
+        cg.Solver(_mesh(), n_levels=3, **dict(dict(mach=0.5), **bad))
+    assert e.value.code == cg.EINVAL
+
+
+def test_batch_with_different_shared_parameters_is_rejected(cg):
+    a = cg.Solver(_mesh(), n_levels=3, mach=0.5)
+    b = cg.Solver(_mesh(), n_levels=3, mach=0.5, cfl_exp=0.3)
+    for s in (a, b):
+        s.init_freestream()
+    with pytest.raises(cg.CgksError):
+        cg.Batch([a, b])
+
+
+def test_single_level_and_tiny_meshes(cg, orc):
+    """Degenerate inputs: two triangles with far field all round (one level), and a
+    2-level hierarchy whose coarse level has one cell per colour class or fewer."""
+    m = sm.two_triangles()
+    g = cg.Solver(m, n_levels=1, mach=0.3)
+    o = orc.Oracle(m, n_levels=1, mach=0.3)
+    W = np.array([[1.0, 0.3, 0.0, 2.0], [1.1, 0.25, 0.05, 2.1]])
+    for s in (g, o):
+        s.set_state(W)
+    Rg, _, _ = g.residual(0)
+    Ro, _, _ = o.residual(0)
+    assert np.abs(Rg - Ro).max() <= 1e-12 * np.abs(Ro).max()
+    assert np.isfinite(g.vcycle())
+    m2 = sm.annulus(4, 1, jitter=0.0, seed=0, nref=1, wall_tag=sm.SLIP)
+    g2 = cg.Solver(m2, n_levels=2, mach=0.3)
+    o2 = orc.Oracle(m2, n_levels=2, mach=0.3)
+    for s in (g2, o2):
+        s.init_freestream()
+    ng = g2.run_cycles(3)
+    no = np.array([o2.vcycle() for _ in range(3)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10, atol=1e-15)
+
+
+def test_mlp_rejects_bad_shapes(cg):
+    import torch
+    net = cg.MLP(seed=0)
+    X = torch.zeros((4, 5), dtype=torch.float32, device="cuda")
+    with pytest.raises((TypeError, ValueError)):
+        net.forward(X, torch.zeros((3, 4), dtype=torch.float32, device="cuda"))
+    with pytest.raises(TypeError):
+        net.forward(X.double(), torch.zeros((4, 4), dtype=torch.float32, device="cuda"))
+    with pytest.raises(cg.CgksError) as e:
+        net.train_step(X, torch.zeros((4, 4), dtype=torch.float32, device="cuda"), -1.0)
+    assert e.value.code == cg.EINVAL
