@@ -128,8 +128,9 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
  * and boundary slots add their ghost state.  Per cell and component the
  * arithmetic is that of a one-thread-per-cell evaluation. */
 constexpr int RMAXC = 64;   /* most cells per reconstruction block */
+constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
 template <int D>
-__global__ void __launch_bounds__(1024) k_recon2(FineDev f, KParams kp0, int cells) {
+__global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int cells) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NC = S::NC, NCOL = S::NCOL;
     constexpr int NK = NQ + D;
@@ -246,32 +247,20 @@ __global__ void __launch_bounds__(1024) k_recon2(FineDev f, KParams kp0, int cel
     const int s = j / NG, k = j - s * NG;
     const int i = i0 + cl;
     const bool live = i < n && j < NS * NG;
-    double Wx[NV], gx[NV][D], W0[NV];
+    double Wx[NV], X[3];
     if (live) {
-#pragma unroll
-        for (int r = 0; r < NV; ++r) W0[r] = f.W[r * n + i];
-        const double ih = 1.0 / f.h[i];
-        double X[3], phi[NQ], dphi[NQ][3], mean[NQ];
+        double phi[NQ], dphi[NQ][3];
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = f.slot_X[((k * D + d) * NS + s) * n + i];
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) mean[m] = f.mean0[m * n + i];
         basis_at<D>(X, phi, dphi);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            double v = W0[q];
+            double v = f.W[q * n + i];
 #pragma unroll
-            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * (phi[m] - mean[m]);
+            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * (phi[m] - f.mean0[m * n + i]);
 #pragma unroll
             for (int d = 0; d < D; ++d) v += coef[q * NK + NQ + d][cl] * X[d];
             Wx[q] = v;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                double gd = coef[q * NK + NQ + d][cl];
-#pragma unroll
-                for (int m = 0; m < NQ; ++m) gd += coef[q * NK + m][cl] * dphi[m][d];
-                gx[q][d] = gd * ih;
-            }
         }
         const KParams kp = localize(kp0, f.ptab, f.pid, i);
         Prim P;
@@ -280,14 +269,23 @@ __global__ void __launch_bounds__(1024) k_recon2(FineDev f, KParams kp0, int cel
     }
     __syncthreads();
     if (!live) return;
-    if (bad[cl]) {
+    const bool guard = bad[cl] != 0;
+    if (guard && j == 0) atomicAdd(f.guard, 1ull);
+    /* gradients from the basis derivatives at the point (recomputed: fewer live
+     * registers across the barrier); the guarded cell is constant */
+    double phi[NQ], dphi[NQ][3], gx[NV][D];
+    basis_at<D>(X, phi, dphi);
+    const double ih = 1.0 / f.h[i];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            Wx[q] = W0[q];
+    for (int q = 0; q < NV; ++q) {
+        if (guard) Wx[q] = f.W[q * n + i];
 #pragma unroll
-            for (int d = 0; d < D; ++d) gx[q][d] = 0.0;
+        for (int d = 0; d < D; ++d) {
+            double gd = coef[q * NK + NQ + d][cl];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) gd += coef[q * NK + m][cl] * dphi[m][d];
+            gx[q][d] = guard ? 0.0 : gd * ih;
         }
-        if (j == 0) atomicAdd(f.guard, 1ull);
     }
     double* out = f.gps + ((size_t)(k * NC) * n + i) * NS + s;
     const size_t cs = (size_t)n * NS;
@@ -1022,7 +1020,7 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
     if (which == 0) {
         /* block = cells per block x faces x Gauss points */
         using S = Shape<D>;
-        const int cells = std::min(block ? block : c->blk_recon, RMAXC);
+        const int cells = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
         k_recon2<D><<<blocks(f.n, cells), cells * S::NS * S::NG, 0, st>>>(f, c->kp, cells);
     } else if (which == 1) {
         const int b = block ? block : c->blk_flux;
