@@ -231,18 +231,28 @@ def _orient_tets(xyz, tets):
     return tets
 
 
-def _refine_tet(xyz, tets):
+def _refine_tet(xyz, tets, surf=None, surf_r=None):
     """1 -> 8 refinement: four corner tetrahedra and the inner octahedron cut
     along the diagonal joining the midpoints of edges 02 and 13.  Child c of
-    parent p is 8 p + c."""
+    parent p is 8 p + c.  surf (optional) gives each node's sphere index (-1:
+    none); the midpoint of an edge with both ends on sphere s is projected
+    onto radius surf_r[s] and inherits s."""
     mid = {}
     pts = [p for p in xyz]
+    sf = list(surf) if surf is not None else None
 
     def midpoint(a, b):
         key = (a, b) if a < b else (b, a)
         if key not in mid:
             mid[key] = len(pts)
-            pts.append(0.5 * (xyz[a] + xyz[b]))
+            p = 0.5 * (xyz[a] + xyz[b])
+            s_new = -1
+            if sf is not None and sf[a] >= 0 and sf[a] == sf[b]:
+                s_new = sf[a]
+                p = p * (surf_r[s_new] / np.linalg.norm(p))
+            pts.append(p)
+            if sf is not None:
+                sf.append(s_new)
         return mid[key]
 
     out = []
@@ -253,7 +263,17 @@ def _refine_tet(xyz, tets):
         out += [(p0, m01, m02, m03), (m01, p1, m12, m13), (m02, m12, p2, m23), (m03, m13, m23, p3),
                 (m02, m13, m01, m03), (m02, m13, m03, m23), (m02, m13, m23, m12), (m02, m13, m12, m01)]
     xyz = np.array(pts)
-    return xyz, _orient_tets(xyz, np.array(out, dtype=np.int64))
+    tets = _orient_tets(xyz, np.array(out, dtype=np.int64))
+    if sf is None:
+        return xyz, tets
+    return xyz, tets, np.array(sf)
+
+
+def _boundary_faces(tets):
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    key = np.sort(faces, axis=1)
+    _, first, count = np.unique(key, axis=0, return_index=True, return_counts=True)
+    return faces[first[count == 1]]
 
 
 def box_tets(n, nref=2, jitter=0.0, seed=0, tags=None, size=1.0):
@@ -287,11 +307,7 @@ def box_tets(n, nref=2, jitter=0.0, seed=0, tags=None, size=1.0):
     for _ in range(nref):
         xyz, tets = _refine_tet(xyz, tets)
         parents.insert(0, np.arange(len(tets), dtype=np.int32) // 8)
-    # boundary faces: faces used by exactly one tetrahedron
-    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
-    key = np.sort(faces, axis=1)
-    _, first, count = np.unique(key, axis=0, return_index=True, return_counts=True)
-    bf = faces[first[count == 1]]
+    bf = _boundary_faces(tets)   # faces used by exactly one tetrahedron
     btags = []
     tol = 1e-12 * size
     for f in bf:
@@ -308,6 +324,66 @@ def box_tets(n, nref=2, jitter=0.0, seed=0, tags=None, size=1.0):
     return Mesh(3, np.ascontiguousarray(xyz), np.ascontiguousarray(tets, dtype=np.int32),
                 np.ascontiguousarray(bf, dtype=np.int32), np.array(btags, dtype=np.int32), parents,
                 dict(kind="box_tets", n=n, nref=nref, jitter=jitter, seed=seed))
+
+
+def sphere_shell(n_az, n_pol, n_rad, r_in=0.5, r_out=6.0, q=1.2, nref=2, jitter=0.0, seed=0,
+                 wall_tag=SLIP, far_tag=FARFIELD):
+    """Spherical shell r in [r_in, r_out] around a unit-diameter sphere: an
+    (azimuth x polar x radial) grid of hexahedra, each split into 6
+    tetrahedra along its index-space diagonal; the polar grid lines collapse
+    into one node per radius and the tetrahedra that degenerate there are
+    dropped; refined 1 -> 8 nref times with the midpoints of edges on the
+    inner or outer sphere projected onto it.  Child c of parent p is 8 p + c."""
+    rng = np.random.default_rng(seed)
+    radii = _radii(n_rad, r_in, r_out, q)
+    nid = {}
+    pts = []
+    for k in range(n_rad + 1):
+        for j in range(n_pol + 1):
+            for i in range(n_az):
+                key = (0 if j in (0, n_pol) else i, j, k)
+                if key in nid:
+                    continue
+                th = math.pi * j / n_pol
+                ph = 2.0 * math.pi * i / n_az
+                r = radii[k]
+                if jitter > 0.0 and 0 < k < n_rad and 0 < j < n_pol:
+                    h = r * math.pi / n_pol
+                    r += jitter * h * rng.uniform(-1.0, 1.0)
+                    th += jitter * (math.pi / n_pol) * rng.uniform(-1.0, 1.0) * 0.5
+                    ph += jitter * (2.0 * math.pi / n_az) * rng.uniform(-1.0, 1.0) * 0.5
+                nid[key] = len(pts)
+                pts.append([r * math.sin(th) * math.cos(ph), r * math.sin(th) * math.sin(ph), r * math.cos(th)])
+    xyz = np.array(pts, dtype=np.float64)
+
+    def node(i, j, k):
+        return nid[(0 if j in (0, n_pol) else i % n_az, j, k)]
+
+    tets = []
+    for k in range(n_rad):
+        for j in range(n_pol):
+            for i in range(n_az):
+                v = [node(i + (c & 1), j + ((c >> 1) & 1), k + ((c >> 2) & 1)) for c in range(8)]
+                for t in _KUHN:
+                    tt = tuple(v[a] for a in t)
+                    if len(set(tt)) == 4:
+                        tets.append(tt)
+    tets = _orient_tets(xyz, np.array(tets, dtype=np.int64))
+    rad = np.linalg.norm(xyz, axis=1)
+    surf = np.where(np.isclose(rad, r_in), 0, np.where(np.isclose(rad, r_out), 1, -1))
+    parents = []
+    for _ in range(nref):
+        xyz, tets, surf = _refine_tet(xyz, tets, surf, (r_in, r_out))
+        parents.insert(0, np.arange(len(tets), dtype=np.int32) // 8)
+    bf = _boundary_faces(tets)
+    on = surf[bf]
+    if not np.all((on == on[:, :1]) & (on >= 0)):
+        raise ValueError("boundary face off the bounding spheres")
+    btags = np.where(on[:, 0] == 0, wall_tag, far_tag).astype(np.int32)
+    return Mesh(3, np.ascontiguousarray(xyz), np.ascontiguousarray(tets, dtype=np.int32),
+                np.ascontiguousarray(bf, dtype=np.int32), btags, parents,
+                dict(kind="sphere_shell", n_az=n_az, n_pol=n_pol, n_rad=n_rad, r_in=r_in, r_out=r_out,
+                     q=q, nref=nref, jitter=jitter, seed=seed))
 
 
 # Named workloads ----------------------------------------------------------

@@ -114,3 +114,59 @@ def test_vcycle_trajectory_parity_3d(cg, orc, case):
     assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
     assert np.abs(gg - go).max() <= 1e-9 * max(np.abs(go).max(), 1e-12)
     np.testing.assert_allclose(ag, ao, rtol=0, atol=1e-8)
+
+
+# ---- the survey's C3 geometry at parity size: Mach 6 flow past a sphere --------------
+
+def _sphere(nref):
+    return sm.sphere_shell(8, 4, 2, nref=nref, jitter=0.1, seed=1)
+
+
+def _sphere_state(o, mach, seed, amp=0.02):
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(seed)
+    r = np.linalg.norm(C, axis=1)
+    ramp = np.tanh((r - 0.5) / 0.4)
+    rho = 1.0 + amp * np.sin(2.0 * C[:, 0]) * np.cos(C[:, 1] + C[:, 2])
+    u = mach * ramp
+    v = mach * amp * np.sin(C[:, 2])
+    w = mach * amp * np.cos(C[:, 0])
+    p = (1.0 + amp * np.cos(C[:, 0] - C[:, 1])) / 1.4
+    W = np.stack([rho, rho * u, rho * v, rho * w, p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)], axis=1)
+    return W, 1e-3 * rng.standard_normal((len(V), 5, 3)), rng.uniform(0.5, 1.0, len(V))
+
+
+def test_sphere_setup_and_residual_parity(cg, orc):
+    mesh = _sphere(2)
+    g, o = _pair(cg, orc, mesh, dim=3, mach=6.0)
+    assert g.sizes == [tuple(s) for s in o.sizes]
+    for l in range(3):
+        cgc, ncg = g.coloring(l)
+        coc, nco = o.coloring(l)
+        assert ncg == nco and np.array_equal(cgc, coc)
+    W, grad, alpha = _sphere_state(o, 6.0, seed=3)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    assert np.abs(Rg - Ro).max() <= 1e-11 * np.abs(Ro).max()
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    # alpha = prod 1/(1 + D^2) falls to ~1e-8 here (Mach-difference terms make D
+    # large); its relative error is ~2 x the relative error of D, itself built
+    # from ratios and square roots: a 1e-10 relative bar
+    np.testing.assert_allclose(ag, ao, rtol=1e-10, atol=1e-13)
+
+
+def test_sphere_vcycle_trajectory_parity(cg, orc):
+    mesh = _sphere(1)
+    g, o = _pair(cg, orc, mesh, n_levels=2, dim=3, mach=6.0)
+    W, _, _ = _sphere_state(o, 6.0, seed=4)
+    for s in (g, o):
+        s.set_state(W, None, None)
+    ng = g.run_cycles(3)
+    no = np.array([o.vcycle() for _ in range(3)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-9 * np.abs(Wo).max()
+    assert g.stats()[1] == o.stats()[1]
