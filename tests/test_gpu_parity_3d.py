@@ -116,7 +116,7 @@ def test_vcycle_trajectory_parity_3d(cg, orc, case):
     np.testing.assert_allclose(ag, ao, rtol=0, atol=1e-8)
 
 
-# ---- the survey's C3 geometry at parity size: Mach 6 flow past a sphere --------------
+# ---- a sphere shell at parity size: Mach 6 flow past a sphere ----------------------
 
 def _sphere(nref):
     return sm.sphere_shell(8, 4, 2, nref=nref, jitter=0.1, seed=1)
