@@ -454,10 +454,13 @@ void ghost(const orc_params& p, int tag, const double* W, const double* g, const
         double Rp = un + 2.0 * c / (gm - 1.0), Rm = uni - 2.0 * ci / (gm - 1.0);
         double ub = 0.5 * (Rp + Rm), cb = 0.25 * (gm - 1.0) * (Rp - Rm);
         double rb, Ub[3], pb;
+        double gfac = 0.5;          /* ghost derivatives / interior derivatives */
         if (ub <= -cb) {            /* supersonic inflow: free stream */
+            gfac = 0.0;
             rb = rhoi; pb = pi;
             for (int d = 0; d < 3; ++d) Ub[d] = Ui[d];
         } else if (ub >= cb) {      /* supersonic outflow: interior */
+            gfac = 1.0;
             rb = rho; pb = pr;
             for (int d = 0; d < 3; ++d) Ub[d] = U[d];
         } else {
@@ -483,10 +486,13 @@ void ghost(const orc_params& p, int tag, const double* W, const double* g, const
             ke += Ub[d] * Ub[d];
         }
         Wg[nv - 1] = pb / (gm - 1.0) + 0.5 * rb * ke;
-        /* derivatives: those of the interior state (zero normal gradient of the
-         * derivatives across the boundary) */
+        /* derivatives: those of the side the ghost comes from on supersonic
+         * faces (zero for the free stream, the interior's for outflow); half
+         * the interior ones on subsonic faces (zero derivatives let a mode grow
+         * at the boundary, copied ones leave a neutral direction of steady
+         * states) */
         if (gg && g)
-            for (int i = 0; i < nv * dim; ++i) gg[i] = g[i];
+            for (int i = 0; i < nv * dim; ++i) gg[i] = gfac * g[i];
         return;
     }
     if (tag == TAG_SLIP) {

@@ -509,11 +509,14 @@ __host__ __device__ __forceinline__ void ghost_state(const KParams& kp, int tag,
         const double Rp = un + 2.0 * c / (gm - 1.0), Rm = uinf_n - 2.0 * cinf / (gm - 1.0);
         const double ub = 0.5 * (Rp + Rm), cb = 0.25 * (gm - 1.0) * (Rp - Rm);
         double rb, pb, Ub[D];
+        double gfac = 0.5;  /* ghost derivatives / interior derivatives */
         if (ub <= -cb) {
+            gfac = 0.0;     /* supersonic inflow: the uniform free stream */
             rb = 1.0; pb = pinf;
 #pragma unroll
             for (int d = 0; d < D; ++d) Ub[d] = kp.u_inf[d];
         } else if (ub >= cb) {
+            gfac = 1.0;     /* supersonic outflow: the interior state */
             rb = rho; pb = p;
 #pragma unroll
             for (int d = 0; d < D; ++d) Ub[d] = U[d];
@@ -541,12 +544,12 @@ __host__ __device__ __forceinline__ void ghost_state(const KParams& kp, int tag,
             k2 += Ub[d] * Ub[d];
         }
         Wg[D + 1] = pb / (gm - 1.0) + 0.5 * rb * k2;
-        /* derivatives: those of the interior state */
+        /* derivatives: a fraction gfac of the interior ones (half on subsonic faces) */
         if constexpr (GRAD) {
 #pragma unroll
             for (int q = 0; q < NV; ++q)
 #pragma unroll
-                for (int d = 0; d < D; ++d) gg[q][d] = g[q][d];
+                for (int d = 0; d < D; ++d) gg[q][d] = gfac * g[q][d];
         }
         return;
     }

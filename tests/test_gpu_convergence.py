@@ -71,3 +71,20 @@ def test_mixed_precision_reaches_the_same_field(cg, mesh, converged):
     err = np.abs(Wm - W).max() / np.abs(W).max()
     print(f"mixed: cycles {len(hist)}, max field difference {err:.2e}", flush=True)
     assert err <= 1e-8
+
+
+def test_tuned_schedule_reaches_the_same_field_faster(cg, mesh, converged):
+    """Three fine steps per cycle with slope relaxation 0.15 and three LU-SGS
+    iterations per coarse level, with the FP32 coarse correction: the same
+    fixed point in fewer cycles."""
+    _, hist0, (W, _, _) = converged
+    print(f"[case] re40 cells={mesh.n_cells} tuned schedule", flush=True)
+    m = cg.Solver(mesh, n_levels=3, precision=cg.MIXED, n_pre_fine=3, slope_relax=0.15, n_sweeps=3, **PARAMS)
+    m.init_freestream()
+    rc, hist = m.solve(tol=1e-10, max_cycles=12000)
+    assert rc == cg.OK and hist[-1] <= 1e-10
+    assert len(hist) < 0.6 * len(hist0)
+    Wm, _, _ = m.get_state()
+    err = np.abs(Wm - W).max() / np.abs(W).max()
+    print(f"tuned: cycles {len(hist)} (plain {len(hist0)}), max field difference {err:.2e}", flush=True)
+    assert err <= 1e-8
