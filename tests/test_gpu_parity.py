@@ -234,10 +234,12 @@ def test_long_trajectory_parity_viscous_steady(cg, orc):
     assert np.abs(Wg - Wo).max() <= 1e-9 * np.abs(Wo).max()
 
 
-def test_batch_equals_individual_solves(cg):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_individual_solves(cg, precision):
     """A batch advances each problem exactly as its own context would: fine states
     bitwise equal after 5 cycles (same kernels, per-problem parameters), norms
-    equal to rounding (the batch reduces per problem in another fixed order)."""
+    equal to rounding (the batch reduces per problem in another fixed order);
+    with the FP64 or the FP32 coarse correction."""
     specs = [(sm.annulus(12, 4, jitter=0.1, seed=1, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=2.0, reynolds=500.0)),
              (sm.annulus(16, 4, jitter=0.2, seed=2, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=0.5, reynolds=2000.0)),
              (sm.annulus(8, 3, jitter=0.1, seed=3, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=4.0, reynolds=1e4,
@@ -245,7 +247,7 @@ def test_batch_equals_individual_solves(cg):
     singles, members = [], []
     for mesh, p in specs:
         for lst in (singles, members):
-            s = cg.Solver(mesh, n_levels=3, **p)
+            s = cg.Solver(mesh, n_levels=3, precision=precision, **p)
             s.init_freestream()
             lst.append(s)
     ref = [s.run_cycles(5) for s in singles]
