@@ -98,11 +98,16 @@ typedef struct cgks_params {
                                   1 = full replacement (Sec. 2.4); same fixed point for any theta in
                                   (0,1].  Default 0.3: with 1 the V-cycle stalls near 3e-4 on a steady
                                   Re 40 cylinder, with 0.3 it converges to round-off */
-    double update_limit;       /* kappa of the update safeguard of coarse LU-SGS updates and prolongation
-                                  corrections: each cell applies the largest fraction 1, 1/2, ..., 2^-10
+    double update_limit;       /* kappa of the update safeguard of fine steps, coarse LU-SGS updates and
+                                  prolongation corrections: each cell applies the largest fraction 1, 1/2, ..., 2^-10
                                   (else 0) of its update that keeps rho and p positive and at least
                                   (1 - kappa) times their current values; kappa <= 0 applies an update
                                   whole if rho, p stay positive, else not at all.  Default 0.5 */
+    int cfl_ramp;              /* implicit-CFL start-up ramp (not in the paper, whose CFL is fixed):
+                                  N > 0 makes the LU-SGS CFL of the k-th V-cycle after the state was
+                                  last set (cgks_init_freestream, cgks_set_state) cfl_imp * min(1, k/N),
+                                  for impulsive hypersonic starts; cycles discarded after a failure
+                                  still count.  Default 0: cfl_imp throughout */
 } cgks_params;
 
 /* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).
@@ -237,7 +242,8 @@ int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gather);
  * union of the problems' hierarchies in device memory; one captured graph
  * replay advances every problem by one V-cycle; per-problem norms are reduced
  * in a fixed order.  The problems' fine states are copied in at creation and
- * back by cgks_batch_solve / cgks_batch_get_state.  Problems stay owned by the
+ * back by cgks_batch_solve / cgks_batch_get_state.  A CFL ramp (cfl_ramp)
+ * counts the batch's V-cycles from its creation.  Problems stay owned by the
  * caller and must outlive the batch.  CGKS_EINVAL if shared parameters differ. */
 typedef struct cgks_batch cgks_batch;
 int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out);

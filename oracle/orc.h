@@ -48,6 +48,7 @@ typedef struct orc_params {
     double skew_limit;
     double slope_relax;
     double update_limit;
+    int cfl_ramp;              /* implicit-CFL start-up ramp length in V-cycles; 0 = none */
 } orc_params;
 
 typedef struct orc_mesh {

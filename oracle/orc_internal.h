@@ -71,6 +71,7 @@ struct orc_ctx {
     std::vector<orc::ReconOp> rop;
     std::string err;
     long long guard_hits = 0, prolong_skips = 0;
+    long long cycles = 0;          /* V-cycles begun since the state was last set */
     bool have_mesh = false;
 };
 

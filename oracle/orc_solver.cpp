@@ -207,6 +207,18 @@ void build_rec(orc_ctx* c, int i, CellRec& r) {
     if (r.guard) ++c->guard_hits;
 }
 
+/* Implicit CFL of the coarse LU-SGS in the current V-cycle.  The paper fixes
+ * it (Sec. 6); with cfl_ramp = N > 0 it rises linearly from cfl_imp / N in the
+ * first V-cycle after the state was set to cfl_imp in the N-th, a start-up
+ * ramp for impulsive hypersonic starts.  Outside a V-cycle the last cycle's
+ * value holds (the first cycle's before any). */
+double implicit_cfl(const orc_ctx* c) {
+    const orc_params& p = c->p;
+    if (p.cfl_ramp <= 0) return p.cfl_imp;
+    const double k = (double)std::max(c->cycles, 1LL);
+    return p.cfl_imp * std::min(1.0, k / (double)p.cfl_ramp);
+}
+
 /* Spectral radius sum and local time steps (convective + viscous). */
 void time_steps(orc_ctx* c, int l, const std::vector<double>& W, std::vector<double>& dte,
                 std::vector<double>& dti) {
@@ -228,7 +240,7 @@ void time_steps(orc_ctx* c, int l, const std::vector<double>& W, std::vector<dou
         if (p.reynolds > 0.0)
             lam += std::max(4.0 / 3.0, p.gamma / p.prandtl) * viscosity(p, pr / rho) / rho * s2 / L.V[i];
         dte[i] = p.cfl_exp * L.V[i] / lam;
-        dti[i] = p.cfl_imp * L.V[i] / lam;
+        dti[i] = implicit_cfl(c) * L.V[i] / lam;
     }
 }
 
@@ -430,24 +442,6 @@ void relax_slopes(orc_ctx* c, const std::vector<double>& gnew) {
     for (size_t k = 0; k < g.size(); ++k) g[k] = g[k] + th * (gnew[k] - g[k]);
 }
 
-/* Explicit fine step of Eq. smo (local time step, Res = -R), applied through
- * update_fraction (a cell takes a fraction theta of its step). */
-void fine_step(orc_ctx* c) {
-    Level& L0 = c->lv[0];
-    const int nv = c->nvar;
-    std::vector<double> R, g, a, dte;
-    fine_residual(c, R, g, a, dte);
-    for (int i = 0; i < L0.n; ++i) {
-        double dW[5];
-        for (int q = 0; q < nv; ++q) dW[q] = -(dte[i] / L0.V[i] * R[i * nv + q]);
-        const double th = update_fraction(c->p, &L0.W[i * nv], dW);
-        if (th > 0.0)
-            for (int q = 0; q < nv; ++q) L0.W[i * nv + q] += th * dW[q];
-    }
-    relax_slopes(c, g);
-    L0.alpha = a;
-}
-
 double density_norm(orc_ctx* c, const std::vector<double>& R) {
     const Level& L0 = c->lv[0];
     const int nv = c->nvar;
@@ -458,6 +452,36 @@ double density_norm(orc_ctx* c, const std::vector<double>& R) {
     }
     return std::sqrt(s / L0.n) / c->p.mach;
 }
+
+/* Explicit fine step of Eq. smo (local time step, Res = -R), applied through
+ * update_fraction (a cell takes a fraction theta of its step).  norm_out, when
+ * given, receives the density-residual norm of the state before the step.
+ * Returns ORC_ENONPHYS when a step is not finite or a new state has rho <= 0 or
+ * p <= 0 (the state is still updated). */
+int fine_step(orc_ctx* c, double* norm_out = nullptr) {
+    Level& L0 = c->lv[0];
+    const int nv = c->nvar, dim = c->dim;
+    std::vector<double> R, g, a, dte;
+    fine_residual(c, R, g, a, dte);
+    if (norm_out) *norm_out = density_norm(c, R);
+    bool ok = true;
+    for (int i = 0; i < L0.n; ++i) {
+        double dW[5];
+        for (int q = 0; q < nv; ++q) {
+            dW[q] = -(dte[i] / L0.V[i] * R[i * nv + q]);
+            ok = ok && std::isfinite(dW[q]);
+        }
+        double* W = &L0.W[i * nv];
+        const double th = update_fraction(c->p, W, dW);
+        if (th > 0.0)
+            for (int q = 0; q < nv; ++q) W[q] += th * dW[q];
+        ok = ok && W[0] > 0.0 && rho_e(dim, W) > 0.0 && std::isfinite(W[nv - 1]);
+    }
+    relax_slopes(c, g);
+    L0.alpha = a;
+    return ok ? ORC_OK : ORC_ENONPHYS;
+}
+
 
 /* Restriction from level l to l+1 (Sec. 5.2): volume-weighted W, summed
  * residual, minimum DF; then the forcing F = Res* - Res(W0). */
@@ -616,6 +640,7 @@ int orc_init_freestream(orc_ctx* c) {
         std::fill(L.F.begin(), L.F.end(), 0.0);
     }
     std::fill(c->lv[0].grad.begin(), c->lv[0].grad.end(), 0.0);
+    c->cycles = 0;
     return ORC_OK;
 }
 
@@ -632,6 +657,7 @@ int orc_set_state(orc_ctx* c, const double* W, const double* gradW, const double
         std::copy(alpha, alpha + L0.n, L0.alpha.begin());
     else
         std::fill(L0.alpha.begin(), L0.alpha.end(), 1.0);
+    c->cycles = 0;
     return ORC_OK;
 }
 
@@ -755,18 +781,11 @@ int orc_vcycle(orc_ctx* c, double* norm_out) {
     int rc = check(c, 0);
     if (rc) return rc;
     const int nl = (int)c->lv.size();
+    ++c->cycles;
     /* Fine pre-smoothing (Eq. smo); the first residual gives the cycle's norm. */
-    for (int s = 0; s < c->p.n_pre_fine; ++s) {
-        Level& L0 = c->lv[0];
-        const int nv = c->nvar;
-        std::vector<double> R, g, a, dte;
-        fine_residual(c, R, g, a, dte);
-        if (s == 0 && norm_out) *norm_out = density_norm(c, R);
-        for (int i = 0; i < L0.n; ++i)
-            for (int q = 0; q < nv; ++q) L0.W[i * nv + q] -= dte[i] / L0.V[i] * R[i * nv + q];
-        relax_slopes(c, g);
-        L0.alpha = a;
-    }
+    bool ok = true;
+    for (int s = 0; s < c->p.n_pre_fine; ++s)
+        ok = fine_step(c, s == 0 ? norm_out : nullptr) == ORC_OK && ok;
     for (int l = 0; l + 1 < nl; ++l) {
         int r2 = orc_restrict(c, l);
         if (r2) return r2;
@@ -775,7 +794,7 @@ int orc_vcycle(orc_ctx* c, double* norm_out) {
     for (int l = nl - 2; l >= 0; --l) prolong_level(c, l);
     for (double v : c->lv[0].W)
         if (!std::isfinite(v)) return ORC_ENONPHYS;
-    return ORC_OK;
+    return ok ? ORC_OK : ORC_ENONPHYS;
 }
 
 int orc_solve(orc_ctx* c, double tol, int max_cycles, int* cycles_out, double* history,

@@ -87,6 +87,7 @@ void make_kparams(cgks_ctx* c) {
     k.omega = p.lusgs_omega;
     k.slope_relax = p.slope_relax;
     k.update_limit = p.update_limit;
+    k.cfl_ramp = p.cfl_ramp;
     k.df_relax = p.df_relax;
     k.df_prolong = p.df_prolong;
     const double a = p.aoa_deg * M_PI / 180.0;
@@ -401,11 +402,14 @@ int upload(cgks_ctx* c) {
     w.npartial = (n + 255) / 256;
     TRY(dalloc(c, &w.partial, w.npartial));
     TRY(dalloc(c, &w.counter, 1));
+    TRY(dalloc(c, &w.ncyc, 1));
     TRY(dalloc(c, &w.status, 1));
     TRY(dalloc(c, &w.skips, 1));
     HIPCHK(hipMemset(w.skips, 0, sizeof(unsigned long long)));
     HIPCHK(hipMemset(w.counter, 0, sizeof(int)));
+    HIPCHK(hipMemset(w.ncyc, 0, sizeof(int)));
     HIPCHK(hipMemset(w.status, 0, sizeof(int)));
+    c->kp.ncyc = w.ncyc;
     TRY(ensure_history(c, 1024));
     HIPCHK(hipDeviceSynchronize());
     return CGKS_OK;
@@ -442,6 +446,7 @@ void cgks_default_params(cgks_params* p) {
     p->skew_limit = 0.2;
     p->slope_relax = 0.3;
     p->update_limit = 0.5;
+    p->cfl_ramp = 0;
 }
 
 const char* cgks_strerror(int code) {
@@ -467,6 +472,7 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (p->precision != CGKS_FP64 && p->precision != CGKS_MIXED) return CGKS_EINVAL;
     if (!(p->slope_relax > 0.0 && p->slope_relax <= 1.0)) return CGKS_EINVAL;
     if (!(p->update_limit <= 1.0)) return CGKS_EINVAL;
+    if (p->cfl_ramp < 0) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
@@ -575,6 +581,7 @@ int cgks_init_freestream(cgks_ctx* c) {
             HIPCHK(hipMemset(D.F, 0, (size_t)nv * n * sizeof(double)));
         }
     }
+    HIPCHK(hipMemsetAsync(c->ws.ncyc, 0, sizeof(int), c->stream));
     HIPCHK(hipDeviceSynchronize());
     return CGKS_OK;
 }
@@ -596,6 +603,7 @@ int cgks_set_state(cgks_ctx* c, const double* W, const double* gradW, const doub
         std::vector<double> a(n, 1.0);
         TRY(h2d(c, c->fine.alpha, a));
     }
+    HIPCHK(hipMemsetAsync(c->ws.ncyc, 0, sizeof(int), c->stream));
     HIPCHK(hipDeviceSynchronize());
     return CGKS_OK;
 }
@@ -873,7 +881,7 @@ bool same_shared_params(const cgks_params& a, const cgks_params& b) {
            a.precision == b.precision && a.tau_c1 == b.tau_c1 && a.tau_c2 == b.tau_c2 &&
            a.weno_gamma_large == b.weno_gamma_large && a.weno_eps == b.weno_eps &&
            a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
-           a.update_limit == b.update_limit &&
+           a.update_limit == b.update_limit && a.cfl_ramp == b.cfl_ramp &&
            ((a.reynolds > 0.0) == (b.reynolds > 0.0));
 }
 

@@ -99,6 +99,7 @@ struct Workspace {
     double* history = nullptr;        /* device norm history */
     int history_cap = 0;
     int* counter = nullptr;           /* device cycle counter */
+    int* ncyc = nullptr;              /* V-cycles begun since the state was set (CFL ramp) */
     unsigned long long* skips = nullptr;
     int* status = nullptr;            /* non-physical flag */
     /* batched solves */
@@ -113,6 +114,8 @@ struct KParams {
     double gamma, K, prandtl, mach, reynolds, mu_inf, Tinf, S_suth, Tw;
     double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax, update_limit;
     int df_relax, df_prolong;
+    int cfl_ramp;                     /* 0: fixed implicit CFL */
+    const int* ncyc;                  /* device: V-cycles begun since the state was set */
     double u_inf[3];
 };
 
@@ -151,7 +154,7 @@ int build_graph(cgks_ctx* c);
 int fail(cgks_ctx* c, int code, const std::string& msg);
 int hip_fail(cgks_ctx* c, hipError_t e, const char* what);
 
-/* kernel launchers (kernels_fine.hip / kernels_coarse.hip) */
+/* kernel launchers (kernels.hip) */
 void launch_fine_residual(cgks_ctx* c, int mode);
 void launch_fine_recon(cgks_ctx* c);
 void launch_fine_kernel(cgks_ctx* c, int which, int block = 0);

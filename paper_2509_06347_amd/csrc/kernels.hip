@@ -49,6 +49,15 @@ __device__ __forceinline__ KParams localize(const KParams& kp, const double* pta
     return k;
 }
 
+/* Implicit CFL of the LU-SGS in the current V-cycle: cfl_imp, or with a ramp of
+ * N cycles cfl_imp * min(1, k/N) in the k-th cycle since the state was set
+ * (k >= 1; outside a cycle the last cycle's value). */
+__device__ __forceinline__ double implicit_cfl(const KParams& kp) {
+    if (kp.cfl_ramp <= 0) return kp.cfl_imp;
+    const int k = *kp.ncyc;
+    return kp.cfl_imp * fmin(1.0, (double)(k > 1 ? k : 1) / (double)kp.cfl_ramp);
+}
+
 template <int D>
 struct Shape {
     static constexpr int NV = D + 2;
@@ -176,7 +185,7 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
                 if (kp.reynolds > 0.0)
                     lam += fmax(4.0 / 3.0, kp.gamma / kp.prandtl) * sutherland(kp, P.p / P.rho) / P.rho * s2 / V;
                 f.dt[i] = kp.cfl_exp * V / lam;
-                f.dti[i] = kp.cfl_imp * V / lam;
+                f.dti[i] = implicit_cfl(kp) * V / lam;
             }
             /* component q of the neighbour averages (ghost averages on boundary faces) */
             double Wq[NS];
@@ -607,7 +616,7 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
     }
     if (kp.reynolds > 0.0) lam += visc * sutherland(kp, P.p / P.rho) / P.rho * s2 / c.V[I];
     const double V = c.V[I];
-    const double dte = kp.cfl_exp * V / lam, dti = kp.cfl_imp * V / lam;
+    const double dte = kp.cfl_exp * V / lam, dti = implicit_cfl(kp) * V / lam;
     c.dte[I] = dte;
     c.dti[I] = dti;
 #pragma unroll
@@ -715,7 +724,7 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
     }
     if (kp.reynolds > 0.0) lam += visc * sutherland(kp, P.p / P.rho) / P.rho * s2 / c.V[I];
     const double V = c.V[I];
-    const double dte = kp.cfl_exp * V / lam, dti = kp.cfl_imp * V / lam;
+    const double dte = kp.cfl_exp * V / lam, dti = implicit_cfl(kp) * V / lam;
     c.dte[I] = dte;
     c.dti[I] = dti;
     double rhs[NV];
@@ -997,8 +1006,12 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_add(double* Wc, const double*
 
 /* Copy the fine state, slopes and DF (three arrays, one launch) to the
  * roll-back buffers while no non-physical state has been flagged. */
+/* Start of a V-cycle: count it (the CFL ramp) and save the state unless a
+ * previous cycle failed. */
 __global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a0, double* b0, int m0, const double* a1, double* b1,
-                                                      int m1, const double* a2, double* b2, int m2, const int* status) {
+                                                      int m1, const double* a2, double* b2, int m2, const int* status,
+                                                      int* ncyc) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ncyc += 1;
     if (*status) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < m0) b0[t] = a0[t];
@@ -1216,7 +1229,7 @@ void launch_save_state(cgks_ctx* c) {
     const int nv = c->nv, dim = c->dim;
     const int m0 = f.n * nv, m1 = f.n * nv * dim, m2 = f.n;
     k_save_if_ok<<<nblk((long)m0 + m1 + m2), BLOCK, 0, c->stream>>>(f.W, f.Wsave, m0, f.grad, f.gsave, m1, f.alpha,
-                                                                    f.asave, m2, c->ws.status);
+                                                                    f.asave, m2, c->ws.status, c->ws.ncyc);
 }
 
 }  // namespace cgks

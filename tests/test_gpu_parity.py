@@ -186,6 +186,31 @@ def test_update_limit_parity(cg, orc, kappa):
     assert sk[0] == sk[1]
 
 
+def test_cfl_ramp_parity(cg, orc):
+    """Impulsive Mach 3 start against an isothermal wall with a 4-cycle ramp of the
+    implicit CFL: per-cycle norms and states track the oracle over the ramp and
+    past it, and the first ramped cycle is bit for bit a fixed-CFL 2.5 cycle."""
+    mesh = sm.annulus(12, 4, jitter=0.1, seed=5, nref=2, wall_tag=sm.ISOTHERMAL)
+    params = dict(mach=3.0, reynolds=1000.0)
+    g, o = _pair(cg, orc, mesh, cfl_ramp=4, **params)
+    W, _, _ = _perturbed(mesh, o, 3.0, seed=9, wall_ramp=True)
+    for s in (g, o):
+        s.set_state(W)
+    ng = g.run_cycles(6)
+    no = np.array([o.vcycle() for _ in range(6)])
+    np.testing.assert_allclose(ng, no, rtol=1e-9)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-8 * np.abs(Wo).max()
+    a = cg.Solver(mesh, n_levels=3, cfl_ramp=4, **params)
+    b = cg.Solver(mesh, n_levels=3, cfl_imp=2.5, **params)
+    for s in (a, b):
+        s.set_state(W)
+        s.run_cycles(1)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+
+
 def test_free_stream_preserved_on_gpu(cg, orc):
     mesh = sm.annulus(13, 5, jitter=0.2, seed=3, nref=2, wall_tag=sm.FARFIELD)
     g = cg.Solver(mesh, n_levels=3, mach=0.7, aoa_deg=12.0)
@@ -234,12 +259,13 @@ def test_long_trajectory_parity_viscous_steady(cg, orc):
     assert np.abs(Wg - Wo).max() <= 1e-9 * np.abs(Wo).max()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_equals_individual_solves(cg, precision):
+@pytest.mark.parametrize("precision,cfl_ramp", [(0, 0), (1, 0), (1, 4)])
+def test_batch_equals_individual_solves(cg, precision, cfl_ramp):
     """A batch advances each problem exactly as its own context would: fine states
     bitwise equal after 5 cycles (same kernels, per-problem parameters), norms
     equal to rounding (the batch reduces per problem in another fixed order);
-    with the FP64 or the FP32 coarse correction."""
+    with the FP64 or the FP32 coarse correction, and with the CFL ramp (the batch
+    counts its cycles from its creation, each context from its initial state)."""
     specs = [(sm.annulus(12, 4, jitter=0.1, seed=1, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=2.0, reynolds=500.0)),
              (sm.annulus(16, 4, jitter=0.2, seed=2, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=0.5, reynolds=2000.0)),
              (sm.annulus(8, 3, jitter=0.1, seed=3, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=4.0, reynolds=1e4,
@@ -247,7 +273,7 @@ def test_batch_equals_individual_solves(cg, precision):
     singles, members = [], []
     for mesh, p in specs:
         for lst in (singles, members):
-            s = cg.Solver(mesh, n_levels=3, precision=precision, **p)
+            s = cg.Solver(mesh, n_levels=3, precision=precision, cfl_ramp=cfl_ramp, **p)
             s.init_freestream()
             lst.append(s)
     ref = [s.run_cycles(5) for s in singles]

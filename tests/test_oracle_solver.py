@@ -263,6 +263,43 @@ def test_lusgs_update_limit_bounds_the_drop(orc, small_mesh, scale):
 
 # ---- 3-D (tetrahedra) ------------------------------------------------------
 
+def test_cfl_ramp_cycles_equal_fixed_cfl_cycles(orc, small_mesh):
+    """The start-up ramp of N cycles runs the k-th V-cycle after a state is set at
+    CFL cfl_imp * k / N: with N = 4 and cfl_imp = 10 the first two cycles are,
+    bit for bit, fixed-CFL cycles at 2.5 and 5 (each scaling exact in binary),
+    every cycle from the fourth on is a plain cfl_imp cycle, and setting a state
+    restarts the count."""
+    kw = dict(mach=0.5, cfl_imp=10.0)
+    ramp = _prepared(orc, small_mesh, cfl_ramp=4, **kw)
+    start = ramp.get_state()
+    states = []
+    for _ in range(5):
+        ramp.vcycle()
+        states.append(ramp.get_state())
+    for k, cfl in ((0, 2.5), (1, 5.0), (3, 10.0), (4, 10.0)):
+        fixed = orc.Oracle(small_mesh, n_levels=3, mach=0.5, cfl_imp=cfl)
+        fixed.set_state(*(start if k == 0 else states[k - 1]))
+        fixed.vcycle()
+        for a, b in zip(fixed.get_state(), states[k]):
+            assert np.array_equal(a, b), (k, cfl)
+    # the third cycle (CFL 7.5) differs from a full-CFL cycle: the ramp is live
+    full = orc.Oracle(small_mesh, n_levels=3, **kw)
+    full.set_state(*states[1])
+    full.vcycle()
+    assert not np.array_equal(full.get_state()[0], states[2][0])
+    # set_state restarts the ramp: the next cycle is a CFL-2.5 cycle again
+    ramp.set_state(*start)
+    ramp.vcycle()
+    for a, b in zip(ramp.get_state(), states[0]):
+        assert np.array_equal(a, b)
+    # outside a V-cycle the implicit time step follows the last cycle's CFL
+    ref = orc.Oracle(small_mesh, n_levels=3, **kw)
+    ramp.vcycle()
+    ref.set_state(*ramp.get_state())
+    np.testing.assert_array_equal(ramp.time_steps(0)[1], 0.5 * ref.time_steps(0)[1])
+    np.testing.assert_array_equal(ramp.time_steps(0)[0], ref.time_steps(0)[0])
+
+
 def _tet_mesh(**kw):
     return sm.box_tets(2, nref=1, jitter=0.1, seed=kw.pop("seed", 6), **kw)
 
