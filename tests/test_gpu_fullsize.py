@@ -1,0 +1,86 @@
+"""GPU (HIP) vs CPU oracle at the benchmark's full size and launch configuration.
+
+Mach 8 viscous cylinder (131,072 / 32,768 / 8,192 cells, isothermal wall) run
+as the benchmark runs it: the solver on torch's current stream, the ramped
+free-stream start, 20 V-cycles of warm-up, then the autotuner's launch shapes.
+At the resulting state (the developed transient the benchmark times) every
+cell's fine residual, new slopes and DF are compared with the oracle, then one
+V-cycle (its norm and every cell's state).  Bars as in the small Mach 8 parity
+cases.  The oracle needs about a minute of one CPU core for this.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tuned():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import bench
+    from paper_2509_06347_amd import cgks
+    mesh, params = bench.workload("cylinder_ns_mach8_131k")
+    print(f"[case] full size: cells={mesh.n_cells} params={params}", flush=True)
+    stream = torch.cuda.current_stream()
+    g = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, **params)
+    bench.initial_state(g, mesh, params)
+    g.run_cycles(20)
+    shapes = g.autotune()
+    print(f"[case] autotuned launch shapes {shapes}", flush=True)
+    return cgks, mesh, params, g, g.get_state()
+
+
+def test_fullsize_fine_residual_parity(tuned, orc):
+    cgks, mesh, params, g, state = tuned
+    o = orc.Oracle(mesh, n_levels=3, **params)
+    o.set_state(*state)
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    assert Rg.shape == (mesh.n_cells, 4)
+    scale = np.abs(Ro).max()
+    err = np.abs(Rg - Ro).max()
+    print(f"residual: max |dR| / max |R| = {err / scale:.2e}", flush=True)
+    assert err <= 1e-11 * scale
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    # alpha reaches ~1e-10 in the shock layer; its relative error is about twice
+    # that of the jump ratios it is built from
+    np.testing.assert_allclose(ag, ao, rtol=1e-10, atol=1e-13)
+
+
+def test_fullsize_vcycle_parity(tuned, orc):
+    cgks, mesh, params, g, state = tuned
+    o = orc.Oracle(mesh, n_levels=3, **params)
+    o.set_state(*state)
+    g.set_state(*state)
+    sg0, so0 = g.stats()[1], o.stats()[1]
+    ng = g.vcycle()
+    no = o.vcycle()
+    print(f"V-cycle norm: GPU {ng:.12e} oracle {no:.12e}", flush=True)
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, gg, ag = g.get_state()
+    Wo, go, ao = o.get_state()
+    assert np.all(np.isfinite(Wg))
+    assert np.abs(Wg - Wo).max() <= 1e-8 * np.abs(Wo).max()
+    assert np.abs(gg - go).max() <= 1e-7 * np.abs(go).max()
+    np.testing.assert_allclose(ag, ao, rtol=0, atol=1e-6)
+    # prolongation corrections limited by the update safeguard in this cycle
+    assert g.stats()[1] - sg0 == o.stats()[1] - so0
+
+
+def test_fullsize_fp32_correction_keeps_the_fp64_norm(tuned):
+    """The FP32 coarse correction acts after the cycle's fine residual, which
+    stays FP64: from the same state its first norm is the FP64 norm, bit for bit."""
+    cgks, mesh, params, g, state = tuned
+    import torch
+    stream = torch.cuda.current_stream()
+    m = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, precision=cgks.MIXED, **params)
+    m.set_state(*state)
+    m.autotune()
+    for s in (g, m):
+        s.set_state(*state)
+    ng, nm = g.vcycle(), m.vcycle()
+    assert ng == nm
+    Wm, _, _ = m.get_state()
+    assert np.all(np.isfinite(Wm)) and Wm[:, 0].min() > 0
