@@ -150,7 +150,8 @@ int cgks_set_stream(cgks_ctx* c, void* stream);
  * upload it to the device.  parent[l] (may be NULL) maps each cell of level l
  * to its agglomerate on level l+1 for l = 0..n_levels-2; a NULL parent[l] or a
  * NULL parent builds that level with Alg. 3 (cell coarsening).  CGKS_EMESH on
- * an invalid mesh.  Host-side set-up; not on the timed path. */
+ * an invalid mesh, CGKS_EINVAL on one without cells or nodes.  Host-side
+ * set-up; not on the timed path. */
 int cgks_mesh_setup(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* const* parent);
 
 /* Sizes of one level: cells and faces (coarse faces are agglomerate pairs). */
@@ -213,12 +214,15 @@ int cgks_prolong(cgks_ctx* c, int level);
 int cgks_vcycle(cgks_ctx* c, double* norm_out);
 
 /* V-cycles until norm <= tol or max_cycles.  history (may be NULL) receives
- * up to history_cap norms.  Returns CGKS_OK, CGKS_NOTCONV or an error. */
+ * up to history_cap norms; cycles_out (may be NULL) the cycles run.  Returns
+ * CGKS_OK, CGKS_NOTCONV (also for max_cycles = 0, with no cycle run) or an
+ * error (CGKS_EINVAL for max_cycles < 0). */
 int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double* history,
                int history_cap);
 
 /* Run n V-cycles with no host synchronisation between them (graph replay);
- * the per-cycle norms stay on the device and are returned in history. */
+ * the per-cycle norms stay on the device and are returned in history.  n = 0
+ * does nothing; n < 0 is CGKS_EINVAL. */
 int cgks_run_cycles(cgks_ctx* c, int n, double* history);
 
 /* Average duration in milliseconds of one kernel of the fine residual at the
@@ -244,11 +248,12 @@ int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gather);
  * in a fixed order.  The problems' fine states are copied in at creation and
  * back by cgks_batch_solve / cgks_batch_get_state.  A CFL ramp (cfl_ramp)
  * counts the batch's V-cycles from its creation.  Problems stay owned by the
- * caller and must outlive the batch.  CGKS_EINVAL if shared parameters differ. */
+ * caller and must outlive the batch.  CGKS_EINVAL if shared parameters differ
+ * or n < 1. */
 typedef struct cgks_batch cgks_batch;
 int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out);
 int cgks_batch_autotune(cgks_batch* b);
-/* ncyc V-cycles; history (may be NULL) is [n][ncyc]. */
+/* ncyc V-cycles; history (may be NULL) is [n][ncyc]; ncyc = 0 does nothing. */
 int cgks_batch_run_cycles(cgks_batch* b, int ncyc, double* history);
 /* Cycles until every problem's norm <= tol (or it failed) or max_cycles.
  * cycles_out[p]: first cycle at or below tol (else cycles run); status_out[p]:
@@ -283,7 +288,8 @@ int cgks_mlp_num_params(void);
 int cgks_mlp_get_weights(cgks_mlp* m, float* flat);
 /* Sets the weights and resets the Adam state (step count and moments). */
 int cgks_mlp_set_weights(cgks_mlp* m, const float* flat);
-/* Y = network(X). */
+/* Y = network(X); n = 0 does nothing.  The loss, gradient and training calls
+ * below need n >= 1 (CGKS_EINVAL otherwise). */
 int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n);
 /* Loss mean_n sum_k (out - Y)^2 (host float) and, if grads_out is not NULL,
  * its gradient in the flat host layout; the weights are not changed. */

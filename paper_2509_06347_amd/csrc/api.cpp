@@ -728,7 +728,8 @@ int cgks_prolong(cgks_ctx* c, int level) {
 
 int cgks_run_cycles(cgks_ctx* c, int ncyc, double* history) {
     TRY(check_level(c, 0));
-    if (ncyc <= 0) return CGKS_OK;
+    if (ncyc < 0) return fail(c, CGKS_EINVAL, "negative cycle count");
+    if (ncyc == 0) return CGKS_OK;
     TRY(ensure_history(c, ncyc));
     TRY(build_graph(c));
     TRY(set_counters(c));
@@ -754,6 +755,8 @@ int cgks_vcycle(cgks_ctx* c, double* norm_out) {
 
 int cgks_solve(cgks_ctx* c, double tol, int max_cycles, int* cycles_out, double* history, int history_cap) {
     TRY(check_level(c, 0));
+    if (max_cycles < 0) return fail(c, CGKS_EINVAL, "negative cycle count");
+    if (cycles_out) *cycles_out = 0;
     int done = 0;
     int chunk = 8;
     std::vector<double> h;
@@ -1075,6 +1078,7 @@ int cgks_batch_autotune(cgks_batch* B) {
 
 int cgks_batch_run_cycles(cgks_batch* B, int ncyc, double* history) {
     if (!B || ncyc < 0) return CGKS_EINVAL;
+    if (ncyc == 0) return CGKS_OK;
     cgks_ctx* c = B->m;
     const int n = (int)B->probs.size();
     TRY(build_graph(c));

@@ -426,7 +426,9 @@ int cgks_mlp_set_weights(cgks_mlp* m, const float* flat) {
 }
 
 int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n) {
-    if (!m || !X || !Y || n <= 0) return CGKS_EINVAL;
+    if (!m || n < 0) return CGKS_EINVAL;
+    if (n == 0) return CGKS_OK;
+    if (!X || !Y) return CGKS_EINVAL;
     int rc = ensure_ws(m, n);
     if (rc) return rc;
     forward(m, X, n);

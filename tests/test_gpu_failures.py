@@ -126,3 +126,36 @@ def test_mlp_rejects_bad_shapes(cg):
     with pytest.raises(cg.CgksError) as e:
         net.train_step(X, torch.zeros((4, 4), dtype=torch.float32, device="cuda"), -1.0)
     assert e.value.code == cg.EINVAL
+
+
+def test_empty_inputs(cg):
+    """Empty inputs: a mesh without cells and a batch without problems are
+    rejected; zero cycles and a zero-row network evaluation do nothing; negative
+    counts and zero-row training are rejected."""
+    import torch
+    m = _mesh()
+    empty = dataclasses.replace(m, cells=m.cells[:0], parents=[])
+    with pytest.raises(cg.CgksError) as e:
+        cg.Solver(empty, n_levels=1, mach=0.5)
+    assert e.value.code == cg.EINVAL
+    with pytest.raises(cg.CgksError) as e:
+        cg.Batch([])
+    assert e.value.code == cg.EINVAL
+    g = cg.Solver(m, n_levels=3, mach=0.5)
+    g.init_freestream()
+    W0, _, _ = g.get_state()
+    assert g.run_cycles(0).shape == (0,)
+    rc, hist = g.solve(max_cycles=0)
+    assert rc == cg.NOTCONV and len(hist) == 0
+    assert cg._lib.cgks_run_cycles(g.ctx, -1, None) == cg.EINVAL
+    b = cg.Batch([g])
+    assert b.run_cycles(0).shape == (1, 0)
+    b.close()
+    np.testing.assert_array_equal(g.get_state()[0], W0)
+    net = cg.MLP(seed=0)
+    X = torch.zeros((0, 5), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((0, 4), dtype=torch.float32, device="cuda")
+    net.forward(X, Y)
+    with pytest.raises(cg.CgksError) as e:
+        net.train_step(X, Y, 1e-3)
+    assert e.value.code == cg.EINVAL

@@ -30,9 +30,10 @@ def cg():
     return cgks
 
 
-def _pair(cg, orc, mesh, n_levels=3, **params):
-    print(f"[case] cells={mesh.n_cells} levels={n_levels} params={params}", flush=True)
-    return cg.Solver(mesh, n_levels=n_levels, **params), orc.Oracle(mesh, n_levels=n_levels, **params)
+def _pair(cg, orc, mesh, n_levels=3, use_parents=True, **params):
+    print(f"[case] cells={mesh.n_cells} levels={n_levels} parents={use_parents} params={params}", flush=True)
+    return (cg.Solver(mesh, n_levels=n_levels, use_parents=use_parents, **params),
+            orc.Oracle(mesh, n_levels=n_levels, use_parents=use_parents, **params))
 
 
 def _perturbed(mesh, o, mach, seed, amp=0.03, slope=2e-3, wall_ramp=False):
@@ -98,11 +99,9 @@ def test_fine_residual_parity(cg, orc, case):
     np.testing.assert_allclose(dg, do, rtol=1e-13)
 
 
-@pytest.mark.parametrize("case", list(CASES))
-def test_coarse_levels_parity(cg, orc, case):
-    mesh, params = CASES[case][0](), CASES[case][1]
-    g, o = _pair(cg, orc, mesh, **params)
-    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=6, wall_ramp="reynolds" in params)
+def _coarse_chain(g, o, W, grad, alpha):
+    """Fine step, restriction, coarse residuals and LU-SGS on levels 1 and 2,
+    prolongations: every intermediate state against the oracle."""
     for s in (g, o):
         s.set_state(W, grad, alpha)
         s.smooth(0, 1)
@@ -130,6 +129,14 @@ def test_coarse_levels_parity(cg, orc, case):
     Wg, _, _ = g.get_state()
     Wo, _, _ = o.get_state()
     assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_coarse_levels_parity(cg, orc, case):
+    mesh, params = CASES[case][0](), CASES[case][1]
+    g, o = _pair(cg, orc, mesh, **params)
+    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=6, wall_ramp="reynolds" in params)
+    _coarse_chain(g, o, W, grad, alpha)
 
 
 @pytest.mark.parametrize("case", ["euler_small", "ns_mach8_small"])
@@ -184,6 +191,54 @@ def test_update_limit_parity(cg, orc, kappa):
     Wo, _, _ = o.get_state()
     assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
     assert sk[0] == sk[1]
+
+
+AGG_CASES = {
+    "2d_ragged_farfield": (lambda: sm.annulus(13, 5, jitter=0.2, seed=3, nref=2, wall_tag=sm.FARFIELD),
+                           dict(mach=0.7, aoa_deg=12.0)),
+    "3d_box_slip": (lambda: sm.box_tets(2, nref=2, jitter=0.1, seed=2, tags={"z0": sm.SLIP}),
+                    dict(dim=3, mach=0.5, aoa_deg=10.0)),
+}
+
+
+@pytest.mark.parametrize("case", list(AGG_CASES))
+def test_agglomerated_hierarchy_parity(cg, orc, case):
+    """Coarse levels built by Alg. 3 agglomeration instead of refinement parents:
+    irregular agglomerates with up to 6 (2-D) or 10 (3-D) faces, the latter
+    beyond the slot-parallel kernels' 8 slots (the per-cell kernels run).
+    Set-up bit-exact, the coarse chain and a 3-cycle trajectory to the bars above."""
+    mesh, params = AGG_CASES[case][0](), AGG_CASES[case][1]
+    g, o = _pair(cg, orc, mesh, use_parents=False, **params)
+    assert g.sizes == [tuple(x) for x in o.sizes]
+    assert g.sizes[1][0] < mesh.n_cells and g.sizes[2][0] < g.sizes[1][0]
+    for l in range(3):
+        cgc, ncg = g.coloring(l)
+        coc, nco = o.coloring(l)
+        assert ncg == nco and np.array_equal(cgc, coc)
+        Vg, Cg = g.cell_geometry(l)
+        Vo, Co = o.cell_geometry(l)
+        np.testing.assert_allclose(Vg, Vo, rtol=1e-13)
+        np.testing.assert_allclose(Cg, Co, rtol=1e-13, atol=1e-14)
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(12)
+    m, dim = params["mach"], params.get("dim", 2)
+    rho = 1.0 + 0.03 * np.sin(2.0 * C[:, 0]) * np.cos(1.5 * C[:, 1])
+    U = np.zeros((mesh.n_cells, dim))
+    U[:, 0] = m * (1.0 + 0.03 * np.cos(C[:, 1]))
+    U[:, 1] = 0.03 * m * np.sin(C[:, 0])
+    p = (1.0 + 0.03 * np.cos(C[:, 0] - C[:, 1])) / 1.4
+    W = np.column_stack([rho, rho[:, None] * U, p / 0.4 + 0.5 * rho * (U ** 2).sum(1)])
+    grad = 1e-3 * rng.standard_normal((mesh.n_cells, dim + 2, dim))
+    alpha = rng.uniform(0.5, 1.0, mesh.n_cells)
+    _coarse_chain(g, o, W, grad, alpha)
+    for s in (g, o):
+        s.set_state(W, None, None)
+    ng = g.run_cycles(3)
+    no = np.array([o.vcycle() for _ in range(3)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
 
 
 def test_cfl_ramp_parity(cg, orc):
