@@ -251,16 +251,18 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
     }
     __syncthreads();
 
-    /* ---- phase 2: (cell, slot, Gauss point) ---- */
-    const int cl = t % cells, j = t / cells;
-    const int s = j / NG, k = j - s * NG;
+    /* ---- phase 2: (cell, slot, Gauss point), slot fastest so that a wave's
+     * stores of one component at one Gauss point are contiguous ---- */
+    const int s = t % NS, r = t / NS;
+    const int cl = r % cells, k = r / cells;
+    const int j = s * NG + k;
     const int i = i0 + cl;
-    const bool live = i < n && j < NS * NG;
+    const bool live = i < n && k < NG;
     double Wx[NV], X[3];
     if (live) {
         double phi[NQ], dphi[NQ][3];
 #pragma unroll
-        for (int d = 0; d < D; ++d) X[d] = f.slot_X[((k * D + d) * NS + s) * n + i];
+        for (int d = 0; d < D; ++d) X[d] = f.slot_X[((size_t)(k * D + d) * n + i) * NS + s];
         basis_at<D>(X, phi, dphi);
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
