@@ -84,7 +84,42 @@ def time_to_tol(cgks, mesh, params, tol, max_cycles, **form):
     dt = time.perf_counter() - t
     W, _, _ = s.get_state()
     return {"seconds": dt if rc == cgks.OK else None, "cycles": int(len(hist)),
-            "final_norm": float(hist[-1]) if len(hist) else None, "converged": rc == cgks.OK}, W
+            "final_norm": float(hist[-1]) if len(hist) else None, "converged": rc == cgks.OK,
+            "ladder": ladder(hist, dt)}, W
+
+
+LADDER = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
+
+
+def ladder(hist, seconds):
+    """First cycle at or below each residual level, and its time pro rata of the
+    run's mean cycle time (the norms are read back in chunks)."""
+    import numpy as np
+    out = {}
+    hist = np.asarray(hist)
+    for L in LADDER:
+        idx = np.nonzero(hist <= L)[0]
+        if len(idx):
+            c = int(idx[0]) + 1
+            out[f"{L:.0e}"] = {"cycles": c, "seconds": seconds * c / len(hist)}
+    return out
+
+
+def explicit_solve(cgks, mesh, params, cap):
+    """The explicit CGKS solver: the fine step alone (one level), from the free
+    stream, until 1e-10 or cap steps."""
+    import torch
+    s = cgks.Solver(mesh, n_levels=1, **params)
+    s.init_freestream()
+    s.autotune()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.init_freestream()
+    rc, hist = s.solve(tol=1e-10, max_cycles=cap)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"steps": int(len(hist)), "seconds": dt, "converged": rc == cgks.OK,
+            "final_norm": float(hist[-1]), "min_norm": float(hist.min()), "ladder": ladder(hist, dt)}
 
 
 def initial_state(solver, mesh, params):
@@ -126,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-cycles", type=int, default=12000)
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--explicit-cap", type=int, default=100000,
+                    help="most steps of the explicit-solver comparison (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -208,6 +245,15 @@ def main():
     ttol = {"workload": "cylinder_ns_mach015_re40_8k", "fine_cells": smesh.n_cells, "tol": 1e-10,
             "plain_fp64": plain, "chosen_form": chosen_t,
             "note": "the benchmark workload's residual does not fall to 1e-10 (unsteady wake)"}
+    # multigrid against the explicit CGKS solver on the same case (the paper's
+    # speedup comparison), at every residual level both reach
+    if args.explicit_cap > 0:
+        ex = explicit_solve(cgks, smesh, sparams, args.explicit_cap)
+        speed = {L: {"plain_fp64": ex["ladder"][L]["seconds"] / plain["ladder"][L]["seconds"],
+                     "chosen_form": ex["ladder"][L]["seconds"] / chosen_t["ladder"][L]["seconds"]}
+                 for L in ex["ladder"] if L in plain["ladder"] and L in chosen_t["ladder"]}
+        ttol["gmg_vs_explicit"] = {"explicit": ex, "speedup": speed,
+                                   "note": "explicit = the fine CGKS step alone (one level) from the free stream"}
 
     out = {"metric": METRIC, "value": value, "unit": "Mcell·V-cycles/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,

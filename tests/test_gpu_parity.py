@@ -266,6 +266,25 @@ def test_cfl_ramp_parity(cg, orc):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("slope_relax", [0.3, 1.0])
+def test_explicit_solver_parity(cg, orc, slope_relax):
+    """The explicit CGKS solver (one level: the fine step alone, the baseline the
+    multigrid is measured against) from the free stream on the steady Re 40
+    cylinder: per-step norms and the state after 10 steps against the oracle,
+    with the relaxed and with the paper's direct slope update."""
+    mesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=2, wall_tag=sm.ISOTHERMAL)
+    g, o = _pair(cg, orc, mesh, n_levels=1, mach=0.15, reynolds=40.0, slope_relax=slope_relax)
+    for s in (g, o):
+        s.init_freestream()
+    ng = g.run_cycles(10)
+    no = np.array([o.vcycle() for _ in range(10)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, gg, _ = g.get_state()
+    Wo, go, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
+    assert np.abs(gg - go).max() <= 1e-9 * np.abs(go).max()
+
+
 def test_free_stream_preserved_on_gpu(cg, orc):
     mesh = sm.annulus(13, 5, jitter=0.2, seed=3, nref=2, wall_tag=sm.FARFIELD)
     g = cg.Solver(mesh, n_levels=3, mach=0.7, aoa_deg=12.0)
