@@ -85,7 +85,9 @@ typedef struct cgks_params {
     int n_pre_fine;            /* fine pre-smoothing steps, default 1 (Sec. 5.2) */
     int n_post;                /* post-smoothing steps: only 0 is supported (Sec. 5.2) */
     int n_sweeps;              /* LU-SGS iterations per coarse level, default 6 (Sec. 6.1) */
-    int df_relax;              /* 1: DF relaxation of LU-SGS (Sec. 4.3); 0: fully implicit */
+    int df_relax;              /* 1: DF relaxation of LU-SGS (Sec. 4.3); 0: fully implicit; 2: one fixed
+                                  relaxation weight relax_beta for every cell (the uniform relaxation
+                                  the DF weighting replaces) */
     int df_prolong;            /* 1: DF-limited prolongation (Eq. prolongation); 0: plain */
     int precision;             /* CGKS_FP64 or CGKS_MIXED */
     double tau_c1;             /* Euler collision time: tau = c1 dt + c2 |dp|/(pl+pr) dt */
@@ -108,6 +110,8 @@ typedef struct cgks_params {
                                   last set (cgks_init_freestream, cgks_set_state) cfl_imp * min(1, k/N),
                                   for impulsive hypersonic starts; cycles discarded after a failure
                                   still count.  Default 0: cfl_imp throughout */
+    double relax_beta;         /* relaxation weight in [0, 1] used when df_relax = 2 (1 = fully implicit,
+                                  0 = explicit steps); default 0.5 */
 } cgks_params;
 
 /* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).

@@ -49,6 +49,7 @@ typedef struct orc_params {
     double slope_relax;
     double update_limit;
     int cfl_ramp;              /* implicit-CFL start-up ramp length in V-cycles; 0 = none */
+    double relax_beta;         /* fixed relaxation weight used when df_relax = 2 */
 } orc_params;
 
 typedef struct orc_mesh {

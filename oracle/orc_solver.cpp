@@ -371,7 +371,8 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
     for (int i = 0; i < L.n; ++i) {
         double sr = 0.0;
         for (int fi : L.cf[i]) sr += L.faces[fi].S * rf[fi];
-        al[i] = p.df_relax ? L.alpha[i] : 1.0;
+        /* relaxation weight: DF (Sec. 4.3), one fixed weight, or fully implicit */
+        al[i] = p.df_relax == 1 ? L.alpha[i] : (p.df_relax == 2 ? p.relax_beta : 1.0);
         D[i] = al[i] * (L.V[i] / dti[i] + 0.5 * sr) + (1.0 - al[i]) * L.V[i] / dte[i];
     }
     std::vector<int> pos(L.n);

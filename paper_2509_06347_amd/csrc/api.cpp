@@ -88,6 +88,7 @@ void make_kparams(cgks_ctx* c) {
     k.slope_relax = p.slope_relax;
     k.update_limit = p.update_limit;
     k.cfl_ramp = p.cfl_ramp;
+    k.relax_beta = p.relax_beta;
     k.df_relax = p.df_relax;
     k.df_prolong = p.df_prolong;
     const double a = p.aoa_deg * M_PI / 180.0;
@@ -447,6 +448,7 @@ void cgks_default_params(cgks_params* p) {
     p->slope_relax = 0.3;
     p->update_limit = 0.5;
     p->cfl_ramp = 0;
+    p->relax_beta = 0.5;
 }
 
 const char* cgks_strerror(int code) {
@@ -473,6 +475,8 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (!(p->slope_relax > 0.0 && p->slope_relax <= 1.0)) return CGKS_EINVAL;
     if (!(p->update_limit <= 1.0)) return CGKS_EINVAL;
     if (p->cfl_ramp < 0) return CGKS_EINVAL;
+    if (p->df_relax < 0 || p->df_relax > 2) return CGKS_EINVAL;
+    if (!(p->relax_beta >= 0.0 && p->relax_beta <= 1.0)) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
@@ -884,7 +888,7 @@ bool same_shared_params(const cgks_params& a, const cgks_params& b) {
            a.precision == b.precision && a.tau_c1 == b.tau_c1 && a.tau_c2 == b.tau_c2 &&
            a.weno_gamma_large == b.weno_gamma_large && a.weno_eps == b.weno_eps &&
            a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
-           a.update_limit == b.update_limit && a.cfl_ramp == b.cfl_ramp &&
+           a.update_limit == b.update_limit && a.cfl_ramp == b.cfl_ramp && a.relax_beta == b.relax_beta &&
            ((a.reynolds > 0.0) == (b.reynolds > 0.0));
 }
 

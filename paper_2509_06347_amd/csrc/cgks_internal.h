@@ -115,6 +115,7 @@ struct KParams {
     double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax, update_limit;
     int df_relax, df_prolong;
     int cfl_ramp;                     /* 0: fixed implicit CFL */
+    double relax_beta;                /* fixed relaxation weight (df_relax = 2) */
     const int* ncyc;                  /* device: V-cycles begun since the state was set */
     double u_inf[3];
 };

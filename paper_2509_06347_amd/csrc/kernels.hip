@@ -58,6 +58,12 @@ __device__ __forceinline__ double implicit_cfl(const KParams& kp) {
     return kp.cfl_imp * fmin(1.0, (double)(k > 1 ? k : 1) / (double)kp.cfl_ramp);
 }
 
+/* Relaxation weight of a coarse cell's LU-SGS (Sec. 4.3): its DF value, one
+ * fixed weight for every cell, or 1 (fully implicit). */
+__device__ __forceinline__ double relax_weight(const KParams& kp, double alpha) {
+    return kp.df_relax == 1 ? alpha : (kp.df_relax == 2 ? kp.relax_beta : 1.0);
+}
+
 template <int D>
 struct Shape {
     static constexpr int NV = D + 2;
@@ -623,7 +629,7 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
     c.dti[I] = dti;
 #pragma unroll
     for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = Res[q] + c.F[q * n + I];
-    const double a = kp.df_relax ? c.alpha[I] : 1.0;
+    const double a = relax_weight(kp, c.alpha[I]);
     const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
     c.D[I] = Dd;
     /* The forward sweep of the first colour has no lower neighbours: its
@@ -735,7 +741,7 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
         rhs[q] = Res[q] + c.F[q * n + I];
         c.rhs[q * n + I] = rhs[q];
     }
-    const double a = kp.df_relax ? c.alpha[I] : 1.0;
+    const double a = relax_weight(kp, c.alpha[I]);
     const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
     c.D[I] = Dd;
     if (I < hi1) {
@@ -840,7 +846,7 @@ __global__ void __launch_bounds__(CBLOCK) k_lusgs(CoarseDev c, KParams kp, int l
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += S * (dT[q] - r * dJ[q]);
     }
-    const T a = kp.df_relax ? (T)c.alpha[I] : (T)1;
+    const T a = (T)relax_weight(kp, c.alpha[I]);
     const T Di = (T)c.D[I];
     if (fwd) {
 #pragma unroll
@@ -892,7 +898,7 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams 
     for (int k = 0; k < c.nslot; ++k)
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += part[q][k][tx];
-    const T a = kp.df_relax ? (T)c.alpha[I] : (T)1;
+    const T a = (T)relax_weight(kp, c.alpha[I]);
     const T Di = (T)c.D[I];
     double dWd[NV];
     if (fwd) {

@@ -266,6 +266,23 @@ def test_cfl_ramp_parity(cg, orc):
         assert np.array_equal(x, y)
 
 
+def test_fixed_relaxation_parity(cg, orc):
+    """One fixed relaxation weight for every coarse cell (df_relax = 2) instead
+    of the DF weights: the coarse chain and a 3-cycle trajectory."""
+    mesh, params = CASES["ragged_farfield"][0](), CASES["ragged_farfield"][1]
+    g, o = _pair(cg, orc, mesh, df_relax=2, relax_beta=0.6, **params)
+    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=13)
+    _coarse_chain(g, o, W, grad, alpha)
+    for s in (g, o):
+        s.set_state(W, None, None)
+    ng = g.run_cycles(3)
+    no = np.array([o.vcycle() for _ in range(3)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
+
+
 @pytest.mark.parametrize("slope_relax", [0.3, 1.0])
 def test_explicit_solver_parity(cg, orc, slope_relax):
     """The explicit CGKS solver (one level: the fine step alone, the baseline the

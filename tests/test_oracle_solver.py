@@ -263,6 +263,30 @@ def test_lusgs_update_limit_bounds_the_drop(orc, small_mesh, scale):
 
 # ---- 3-D (tetrahedra) ------------------------------------------------------
 
+def test_fixed_relaxation_reduces_to_pinned_cases(orc, small_mesh):
+    """df_relax = 2 (one relaxation weight beta for every coarse cell): beta = 1 is
+    the fully implicit LU-SGS bit for bit, and a fixed beta is the DF relaxation
+    with alpha = beta in every cell (whose alpha -> 0 limit is pinned above)."""
+    def coarse(**kw):
+        o = _prepared(orc, small_mesh, mach=0.5, **kw)
+        o.smooth(0, 1)
+        o.restrict(0)
+        return o
+    a, b = coarse(df_relax=2, relax_beta=1.0), coarse(df_relax=0)
+    for o in (a, b):
+        o.smooth(1, 2)
+    Wa, Wb = a.get_level_state(1)[0], b.get_level_state(1)[0]
+    assert np.array_equal(Wa, Wb)
+    c, d = coarse(df_relax=2, relax_beta=0.6), coarse(df_relax=1)
+    n1 = d.get_level_state(1)[3].shape[0]
+    d.set_level_state(1, alpha=np.full(n1, 0.6))
+    for o in (c, d):
+        o.smooth(1, 2)
+    Wc, Wd = c.get_level_state(1)[0], d.get_level_state(1)[0]
+    assert np.array_equal(Wc, Wd)
+    assert not np.array_equal(Wc, Wa)
+
+
 def test_cfl_ramp_cycles_equal_fixed_cfl_cycles(orc, small_mesh):
     """The start-up ramp of N cycles runs the k-th V-cycle after a state is set at
     CFL cfl_imp * k / N: with N = 4 and cfl_imp = 10 the first two cycles are,
