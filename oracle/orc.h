@@ -50,6 +50,7 @@ typedef struct orc_params {
     double update_limit;
     int cfl_ramp;              /* implicit-CFL start-up ramp length in V-cycles; 0 = none */
     double relax_beta;         /* fixed relaxation weight used when df_relax = 2 */
+    int shared_residual;       /* 1: restrict the last fine step's input state and residual */
 } orc_params;
 
 typedef struct orc_mesh {

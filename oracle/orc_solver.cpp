@@ -456,15 +456,22 @@ double density_norm(orc_ctx* c, const std::vector<double>& R) {
 
 /* Explicit fine step of Eq. smo (local time step, Res = -R), applied through
  * update_fraction (a cell takes a fraction theta of its step).  norm_out, when
- * given, receives the density-residual norm of the state before the step.
+ * given, receives the density-residual norm of the state before the step;
+ * W_in and res_out, when given, receive that state and its Res = -R.
  * Returns ORC_ENONPHYS when a step is not finite or a new state has rho <= 0 or
  * p <= 0 (the state is still updated). */
-int fine_step(orc_ctx* c, double* norm_out = nullptr) {
+int fine_step(orc_ctx* c, double* norm_out = nullptr, std::vector<double>* W_in = nullptr,
+              std::vector<double>* res_out = nullptr) {
     Level& L0 = c->lv[0];
     const int nv = c->nvar, dim = c->dim;
     std::vector<double> R, g, a, dte;
     fine_residual(c, R, g, a, dte);
     if (norm_out) *norm_out = density_norm(c, R);
+    if (W_in) *W_in = L0.W;
+    if (res_out) {
+        res_out->resize(R.size());
+        for (size_t k = 0; k < R.size(); ++k) (*res_out)[k] = -R[k];
+    }
     bool ok = true;
     for (int i = 0; i < L0.n; ++i) {
         double dW[5];
@@ -486,15 +493,17 @@ int fine_step(orc_ctx* c, double* norm_out = nullptr) {
 
 /* Restriction from level l to l+1 (Sec. 5.2): volume-weighted W, summed
  * residual, minimum DF; then the forcing F = Res* - Res(W0). */
-void restrict_level(orc_ctx* c, int l, const std::vector<double>& res_fine) {
+void restrict_level(orc_ctx* c, int l, const std::vector<double>& res_fine,
+                    const std::vector<double>* W_fine = nullptr) {
     const int nv = c->nvar;
     Level& F = c->lv[l];
     Level& G = c->lv[l + 1];
+    const std::vector<double>& Wf = W_fine ? *W_fine : F.W;
     for (int I = 0; I < G.n; ++I) {
         double w[5] = {0, 0, 0, 0, 0}, r[5] = {0, 0, 0, 0, 0}, amin = 1e300;
         for (int i : G.children[I]) {
             for (int q = 0; q < nv; ++q) {
-                w[q] += F.V[i] * F.W[i * nv + q];
+                w[q] += F.V[i] * Wf[i * nv + q];
                 r[q] += res_fine[i * nv + q];
             }
             amin = std::min(amin, F.alpha[i]);
@@ -783,13 +792,24 @@ int orc_vcycle(orc_ctx* c, double* norm_out) {
     if (rc) return rc;
     const int nl = (int)c->lv.size();
     ++c->cycles;
-    /* Fine pre-smoothing (Eq. smo); the first residual gives the cycle's norm. */
+    /* Fine pre-smoothing (Eq. smo); the first residual gives the cycle's norm.
+     * With shared_residual the last step's input state and residual are the
+     * ones restricted (one fine residual per smoothing step, none extra). */
+    const bool shared = c->p.shared_residual && nl > 1;
+    std::vector<double> Wkeep, reskeep;
     bool ok = true;
-    for (int s = 0; s < c->p.n_pre_fine; ++s)
-        ok = fine_step(c, s == 0 ? norm_out : nullptr) == ORC_OK && ok;
+    for (int s = 0; s < c->p.n_pre_fine; ++s) {
+        const bool keep = shared && s == c->p.n_pre_fine - 1;
+        ok = fine_step(c, s == 0 ? norm_out : nullptr, keep ? &Wkeep : nullptr, keep ? &reskeep : nullptr) ==
+                 ORC_OK && ok;
+    }
     for (int l = 0; l + 1 < nl; ++l) {
-        int r2 = orc_restrict(c, l);
-        if (r2) return r2;
+        if (l == 0 && shared) {
+            restrict_level(c, 0, reskeep, &Wkeep);
+        } else {
+            int r2 = orc_restrict(c, l);
+            if (r2) return r2;
+        }
         for (int s = 0; s < c->p.n_sweeps; ++s) lusgs_iter(c, l + 1, false);
     }
     for (int l = nl - 2; l >= 0; --l) prolong_level(c, l);

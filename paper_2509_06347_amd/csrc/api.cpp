@@ -158,13 +158,25 @@ void enqueue_restrict(cgks_ctx* c, int l) {
     launch_coarse_rhs(c, l + 1, COARSE_FORCING);
 }
 
-/* One V-cycle: fine pre-smoothing, restriction, coarse LU-SGS, prolongation. */
+/* One V-cycle: fine pre-smoothing, restriction, coarse LU-SGS, prolongation.
+ * With shared_residual the last fine step keeps its input state and residual,
+ * and those are restricted (no second fine residual evaluation). */
 void enqueue_vcycle(cgks_ctx* c) {
     const int nl = (int)c->hl.size();
+    const bool shared = c->p.shared_residual && nl > 1;
     launch_save_state(c);
-    for (int s = 0; s < c->p.n_pre_fine; ++s) launch_fine_residual(c, s == 0 ? FINE_STEP_NORM : FINE_STEP);
+    for (int s = 0; s < c->p.n_pre_fine; ++s) {
+        int mode = s == 0 ? FINE_STEP_NORM : FINE_STEP;
+        if (shared && s == c->p.n_pre_fine - 1) mode |= FINE_KEEP;
+        launch_fine_residual(c, mode);
+    }
     for (int l = 0; l + 1 < nl; ++l) {
-        enqueue_restrict(c, l);
+        if (l == 0 && shared) {
+            launch_restrict(c, 0, c->fine.Wpre);
+            launch_coarse_rhs(c, 1, COARSE_FORCING);
+        } else {
+            enqueue_restrict(c, l);
+        }
         launch_lusgs_iters(c, l + 1, c->p.n_sweeps);
     }
     for (int l = nl - 2; l >= 0; --l) launch_prolong(c, l);
@@ -327,6 +339,7 @@ int upload(cgks_ctx* c) {
     TRY(dalloc(c, &f.dt, n));
     TRY(dalloc(c, &f.dti, n));
     TRY(dalloc(c, &f.res, (size_t)nv * n));
+    TRY(dalloc(c, &f.Wpre, (size_t)nv * n));
     TRY(dalloc(c, &f.guard, 1));
     HIPCHK(hipMemset(f.guard, 0, sizeof(unsigned long long)));
 
@@ -449,6 +462,7 @@ void cgks_default_params(cgks_params* p) {
     p->update_limit = 0.5;
     p->cfl_ramp = 0;
     p->relax_beta = 0.5;
+    p->shared_residual = 0;
 }
 
 const char* cgks_strerror(int code) {
@@ -477,6 +491,7 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (p->cfl_ramp < 0) return CGKS_EINVAL;
     if (p->df_relax < 0 || p->df_relax > 2) return CGKS_EINVAL;
     if (!(p->relax_beta >= 0.0 && p->relax_beta <= 1.0)) return CGKS_EINVAL;
+    if (p->shared_residual != 0 && p->shared_residual != 1) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
@@ -889,6 +904,7 @@ bool same_shared_params(const cgks_params& a, const cgks_params& b) {
            a.weno_gamma_large == b.weno_gamma_large && a.weno_eps == b.weno_eps &&
            a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
            a.update_limit == b.update_limit && a.cfl_ramp == b.cfl_ramp && a.relax_beta == b.relax_beta &&
+           a.shared_residual == b.shared_residual &&
            ((a.reynolds > 0.0) == (b.reynolds > 0.0));
 }
 

@@ -69,6 +69,7 @@ struct FineDev {
     double *fF, *fG, *fa;             /* [nv][ngp*nf], [nv][ngp*nf], [ngp*nf] */
     double *R, *gnew, *anew, *dt, *dti;
     double *res;                      /* -R of the restriction evaluation */
+    double *Wpre;                     /* input state of a fine step whose residual is restricted */
     unsigned long long* guard;        /* positivity-guard hit counter */
     /* batched solves: problem id per cell / per face and the per-problem table */
     const int *pid, *fpid;
@@ -161,7 +162,7 @@ void launch_fine_recon(cgks_ctx* c);
 void launch_fine_kernel(cgks_ctx* c, int which, int block = 0);
 void launch_coarse_rhs(cgks_ctx* c, int level, int mode);
 void launch_lusgs(cgks_ctx* c, int level);
-void launch_restrict(cgks_ctx* c, int level);
+void launch_restrict(cgks_ctx* c, int level, const double* Wfine = nullptr);
 void launch_prolong(cgks_ctx* c, int level);
 void launch_norm_finalize(cgks_ctx* c);
 void launch_save_state(cgks_ctx* c);
@@ -171,6 +172,8 @@ void launch_lusgs_iters(cgks_ctx* c, int level, int n);
 
 /* modes of launch_fine_residual */
 enum { FINE_EVAL = 0, FINE_STEP = 1, FINE_STEP_NORM = 2, FINE_RESTRICT = 3 };
+/* flag on a step mode: also keep -R in res and the step's input state in Wpre */
+enum { FINE_KEEP = 8 };
 /* modes of launch_coarse_rhs */
 enum { COARSE_RHS = 0, COARSE_FORCING = 1 };
 }  // namespace cgks

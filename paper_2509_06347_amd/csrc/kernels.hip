@@ -435,6 +435,8 @@ template <int D>
 __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mode, double* partial, int* status) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NS = S::NS, NG = S::NG;
+    const bool keep = (mode & FINE_KEEP) != 0;
+    mode &= ~FINE_KEEP;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = f.n, nf = f.nf;
     double contrib = 0.0;
@@ -495,6 +497,13 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
                 finite = finite && isfinite(dW[q]);
             }
             const double fr = update_fraction<D>(Wo, dW, kp.update_limit);
+            if (keep) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    f.res[q * n + i] = -R[q];
+                    f.Wpre[q * n + i] = Wo[q];
+                }
+            }
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 Wn[q] = fr > 0.0 ? Wo[q] + fr * dW[q] : Wo[q];
@@ -1048,7 +1057,8 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
         k_flux<D><<<blocks((long)f.nf * f.ngp, b), b, 0, st>>>(f, c->kp);
     } else {
         /* the norm partials use a fixed 256-thread block */
-        const int b = (mode == FINE_STEP_NORM && !f.pid) ? BLOCK : (block ? block : c->blk_gather);
+        const int m = mode & ~FINE_KEEP;
+        const int b = (m == FINE_STEP_NORM && !f.pid) ? BLOCK : (block ? block : c->blk_gather);
         k_gather<D><<<blocks(f.n, b), b, 0, st>>>(f, c->kp, mode, c->ws.partial, c->ws.status);
     }
 }
@@ -1070,7 +1080,7 @@ static void fine_residual(cgks_ctx* c, int mode) {
     fine_kernel<D>(c, 0, 0, mode);
     fine_kernel<D>(c, 1, 0, mode);
     fine_kernel<D>(c, 2, 0, mode);
-    if (mode == FINE_STEP_NORM) {
+    if ((mode & ~FINE_KEEP) == FINE_STEP_NORM) {
         if (f.pid) {
             k_norm_batch<<<c->ws.nprob, BLOCK, 0, st>>>(f.r2, c->ws.poff, c->ws.ptab, c->ws.history,
                                                          c->ws.history_cap, c->ws.counter, c->ws.nprob);
@@ -1187,12 +1197,12 @@ void launch_coarse_update(cgks_ctx* c, int level) {
     }
 }
 
-void launch_restrict(cgks_ctx* c, int level) {
+void launch_restrict(cgks_ctx* c, int level, const double* Wfine) {
     CoarseDev& G = c->coarse[level];
     const double *Wf, *Vf, *rf, *af;
     int nfine;
     if (level == 0) {
-        Wf = c->fine.W; Vf = c->fine.V; rf = c->fine.res; af = c->fine.alpha; nfine = c->fine.n;
+        Wf = Wfine ? Wfine : c->fine.W; Vf = c->fine.V; rf = c->fine.res; af = c->fine.alpha; nfine = c->fine.n;
     } else {
         CoarseDev& F = c->coarse[level - 1];
         Wf = F.W; Vf = F.V; rf = F.rhs; af = F.alpha; nfine = F.n;

@@ -88,3 +88,4 @@ def test_tuned_schedule_reaches_the_same_field_faster(cg, mesh, converged):
     err = np.abs(Wm - W).max() / np.abs(W).max()
     print(f"tuned: cycles {len(hist)} (plain {len(hist0)}), max field difference {err:.2e}", flush=True)
     assert err <= 1e-8
+

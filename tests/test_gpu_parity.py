@@ -266,6 +266,30 @@ def test_cfl_ramp_parity(cg, orc):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shared_residual_parity(cg, orc, precision):
+    """The V-cycle with one fine residual evaluation (shared_residual = 1): per-cycle
+    norms and the state after 8 cycles against the oracle, from a perturbed
+    state (FP32 coarse correction: the norms, which come first in each cycle,
+    to 1e-10 for the first cycle; the state to the FP32 correction's bar)."""
+    mesh, params = CASES["euler_small"][0](), CASES["euler_small"][1]
+    g, o = _pair(cg, orc, mesh, shared_residual=1, precision=precision, **params)
+    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=14)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+    ng = g.run_cycles(8)
+    no = np.array([o.vcycle() for _ in range(8)])
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    if precision == 0:
+        np.testing.assert_allclose(ng, no, rtol=1e-10)
+        assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
+    else:
+        np.testing.assert_allclose(ng[0], no[0], rtol=1e-12)
+        np.testing.assert_allclose(ng, no, rtol=1e-4)
+        assert np.abs(Wg - Wo).max() <= 1e-5 * np.abs(Wo).max()
+
+
 def test_fixed_relaxation_parity(cg, orc):
     """One fixed relaxation weight for every coarse cell (df_relax = 2) instead
     of the DF weights: the coarse chain and a 3-cycle trajectory."""

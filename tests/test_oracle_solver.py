@@ -263,6 +263,35 @@ def test_lusgs_update_limit_bounds_the_drop(orc, small_mesh, scale):
 
 # ---- 3-D (tetrahedra) ------------------------------------------------------
 
+def test_shared_residual_cycle_is_a_composition_of_pinned_steps(orc, small_mesh):
+    """shared_residual = 1: the V-cycle restricts W^n with its own residual, solves
+    the coarse levels, takes the fine step from W^n and prolongs onto its
+    result.  Bit for bit: restrict(0) at W^n, 6 LU-SGS iterations, restrict(1),
+    6 iterations, prolong(1), then (W^n, slopes and DF of W^n restored: restrict
+    stores the new DF, which the reconstruction uses) one fine step and
+    prolong(0), each pinned above."""
+    A = _prepared(orc, small_mesh, mach=0.5, shared_residual=1)
+    B = _prepared(orc, small_mesh, mach=0.5)
+    C = _prepared(orc, small_mesh, mach=0.5)
+    A.smooth(0, 1)                    # a state with slopes and DF values
+    S = A.get_state()
+    for o in (A, B, C):
+        o.set_state(*S)
+    A.vcycle()
+    B.restrict(0)
+    B.smooth(1, 6)
+    B.restrict(1)
+    B.smooth(2, 6)
+    B.prolong(1)
+    B.set_state(*S)
+    B.smooth(0, 1)
+    B.prolong(0)
+    for x, y in zip(A.get_state(), B.get_state()):
+        assert np.array_equal(x, y)
+    C.vcycle()                        # the paper's cycle restricts the smoothed state
+    assert not np.array_equal(C.get_state()[0], A.get_state()[0])
+
+
 def test_fixed_relaxation_reduces_to_pinned_cases(orc, small_mesh):
     """df_relax = 2 (one relaxation weight beta for every coarse cell): beta = 1 is
     the fully implicit LU-SGS bit for bit, and a fixed beta is the DF relaxation
