@@ -49,8 +49,8 @@ RECON_BYTES_PER_CELL_2D = 8 * (4 + 8 + 3 + 3 + 6 + 12 + 5 + 45) + 4 * 6 + 8 * (7
 # FETCH_SIZE and WRITE_SIZE counter runs of this script scaled by the counters'
 # reading for a plain copy of known size (FETCH x2.0, WRITE x1.0).  Valid only
 # for the kernel source the counters were taken with; absent when not taken.
-TRAFFIC_BYTES = {("cylinder_ns_mach8_131k", "k_recon2"): 181.4e6,
-                 ("cylinder_ns_mach8_131k", "k_flux"): 146.6e6}
+TRAFFIC_BYTES = {("cylinder_ns_mach8_131k", "k_recon2"): 180.8e6,
+                 ("cylinder_ns_mach8_131k", "k_flux"): 149.4e6}
 
 
 def workload(name):

@@ -140,7 +140,8 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
  * time steps.  Phase 2, one thread per (cell, face slot, Gauss point): value
  * and gradient of every component at its point; the cell's positivity guard
  * is an LDS flag over its points; states are written [k][component][cell][slot]
- * and boundary slots add their ghost state.  Per cell and component the
+ * and boundary slots add their ghost state.  Phase 1 also leaves the cell's
+ * state and basis means in LDS for phase 2.  Per cell and component the
  * arithmetic is that of a one-thread-per-cell evaluation. */
 constexpr int RMAXC = 64;   /* most cells per reconstruction block */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
@@ -150,6 +151,8 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NC = S::NC, NCOL = S::NCOL;
     constexpr int NK = NQ + D;
     __shared__ double coef[NV * NK][RMAXC];
+    __shared__ double wsh[NV][RMAXC];      /* cell states, for phase 2 */
+    __shared__ double msh[NQ][RMAXC];      /* basis means, for phase 2 */
     __shared__ int bad[RMAXC];
     const int t = threadIdx.x;
     const int n = f.n, nf = f.nf;
@@ -208,6 +211,8 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
             double mean[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) mean[k] = f.mean0[k * n + i];
+            wsh[q][cl] = W0[q];
+            for (int k = q; k < NQ; k += NV) msh[k][cl] = mean[k];
             double a[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) a[k] = 0.0;
@@ -270,11 +275,14 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = f.slot_X[((size_t)(k * D + d) * n + i) * NS + s];
         basis_at<D>(X, phi, dphi);
+        double pm[NQ];
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) pm[m] = phi[m] - msh[m][cl];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            double v = f.W[q * n + i];
+            double v = wsh[q][cl];
 #pragma unroll
-            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * (phi[m] - f.mean0[m * n + i]);
+            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * pm[m];
 #pragma unroll
             for (int d = 0; d < D; ++d) v += coef[q * NK + NQ + d][cl] * X[d];
             Wx[q] = v;
@@ -295,7 +303,7 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
     const double ih = 1.0 / f.h[i];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        if (guard) Wx[q] = f.W[q * n + i];
+        if (guard) Wx[q] = wsh[q][cl];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             double gd = coef[q * NK + NQ + d][cl];
