@@ -302,7 +302,8 @@ int upload(cgks_ctx* c) {
             for (int d = 0; d < dim; ++d) {
                 sn[((size_t)d * ns + s) * n + i] = sg * F.n[d];
                 for (int g = 0; g < ng; ++g)
-                    sX[(((size_t)g * dim + d) * n + i) * ns + s] = (F.gp[g][d] - H.C[(size_t)i * dim + d]) * ih;
+                    sX[dim == 2 ? (((size_t)g * dim + d) * n + i) * ns + s : (((size_t)g * dim + d) * ns + s) * n + i] =
+                        (F.gp[g][d] - H.C[(size_t)i * dim + d]) * ih;
             }
         }
     }

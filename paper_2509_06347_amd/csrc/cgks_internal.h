@@ -58,7 +58,8 @@ struct FineDev {
     int *slot_nbr;                    /* [nslot][n]: neighbour or -1 */
     int *slot_tag;                    /* [nslot][n]: boundary tag of the slot's face (0 interior) */
     double *slot_S, *slot_n;          /* [nslot][n] face area, [dim][nslot][n] outward unit normal */
-    double *slot_X;                   /* [ngp][dim][n][nslot] Gauss points (x - x_c) / h */
+    double *slot_X;                   /* Gauss points (x - x_c) / h: [ngp][dim][n][nslot] for triangles,
+                                         [ngp][dim][nslot][n] for tetrahedra */
     int *fL, *fR;
     int *fslot;                       /* per face: slot in L | (slot in R, 7 on a boundary) << 3 */
     double *fn, *fS;                  /* fn [dim][nf] */

@@ -262,10 +262,19 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
     }
     __syncthreads();
 
-    /* ---- phase 2: (cell, slot, Gauss point), slot fastest so that a wave's
-     * stores of one component at one Gauss point are contiguous ---- */
-    const int s = t % NS, r = t / NS;
-    const int cl = r % cells, k = r / cells;
+    /* ---- phase 2: (cell, slot, Gauss point).  Triangles: slot fastest, so that
+     * a wave's stores of one component at one Gauss point are contiguous.
+     * Tetrahedra: cell fastest (slot-fastest lanes measured 1.8x slower). ---- */
+    int s, cl, k;
+    if constexpr (D == 2) {
+        s = t % NS;
+        cl = (t / NS) % cells;
+        k = t / (NS * cells);
+    } else {
+        cl = t % cells;
+        s = (t / cells) / NG;
+        k = (t / cells) - s * NG;
+    }
     const int j = s * NG + k;
     const int i = i0 + cl;
     const bool live = i < n && k < NG;
@@ -273,7 +282,8 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
     if (live) {
         double phi[NQ], dphi[NQ][3];
 #pragma unroll
-        for (int d = 0; d < D; ++d) X[d] = f.slot_X[((size_t)(k * D + d) * n + i) * NS + s];
+        for (int d = 0; d < D; ++d)
+            X[d] = f.slot_X[D == 2 ? ((size_t)(k * D + d) * n + i) * NS + s : ((size_t)(k * D + d) * NS + s) * n + i];
         basis_at<D>(X, phi, dphi);
         double pm[NQ];
 #pragma unroll
