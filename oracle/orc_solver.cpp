@@ -204,7 +204,10 @@ void build_rec(orc_ctx* c, int i, CellRec& r) {
             if (!physical(c->p, W)) r.guard = true;
         }
     }
-    if (r.guard) ++c->guard_hits;
+    if (r.guard) {
+#pragma omp atomic
+        ++c->guard_hits;
+    }
 }
 
 /* Implicit CFL of the coarse LU-SGS in the current V-cycle.  The paper fixes
@@ -227,6 +230,7 @@ void time_steps(orc_ctx* c, int l, const std::vector<double>& W, std::vector<dou
     const orc_params& p = c->p;
     dte.assign(L.n, 0.0);
     dti.assign(L.n, 0.0);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L.n; ++i) {
         double rho, U[3], pr;
         prim(p, &W[i * nv], &rho, U, &pr);
@@ -252,9 +256,11 @@ void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew
     std::vector<double> dti;
     time_steps(c, 0, L0.W, dte, dti);
     std::vector<CellRec> rec(L0.n);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L0.n; ++i) build_rec(c, i, rec[i]);
     const int nf = (int)L0.faces.size();
     std::vector<double> Ff((size_t)nf * nv, 0.0), Gf((size_t)nf * nv, 0.0), af(nf, 1.0);
+#pragma omp parallel for schedule(static)
     for (int fi = 0; fi < nf; ++fi) {
         const Face& f = L0.faces[fi];
         double dt = dte[f.L];
@@ -278,6 +284,7 @@ void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew
     R.assign((size_t)L0.n * nv, 0.0);
     gnew.assign((size_t)L0.n * nv * dim, 0.0);
     anew.assign(L0.n, 1.0);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L0.n; ++i) {
         for (int fi : L0.cf[i]) {
             const Face& f = L0.faces[fi];
@@ -303,6 +310,7 @@ void coarse_res(orc_ctx* c, int l, const std::vector<double>& W, std::vector<dou
     const Level& L = c->lv[l];
     Res.assign((size_t)L.n * nv, 0.0);
     std::vector<double> Ff(L.faces.size() * nv);
+#pragma omp parallel for schedule(static)
     for (size_t fi = 0; fi < L.faces.size(); ++fi) {
         const Face& f = L.faces[fi];
         double Wr[5], F[5];
@@ -313,6 +321,7 @@ void coarse_res(orc_ctx* c, int l, const std::vector<double>& W, std::vector<dou
         kfvs_point(c->p, &W[f.L * nv], Wr, f.n, F);
         for (int q = 0; q < nv; ++q) Ff[fi * nv + q] = f.S * F[q];
     }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L.n; ++i)
         for (int fi : L.cf[i]) {
             const Face& f = L.faces[fi];
@@ -366,8 +375,10 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
     for (size_t k = 0; k < rhs.size(); ++k) rhs[k] = Res[k] + L.F[k];
     time_steps(c, l, L.W, dte, dti);
     std::vector<double> rf(L.faces.size());
+#pragma omp parallel for schedule(static)
     for (size_t fi = 0; fi < L.faces.size(); ++fi) rf[fi] = spectral_radius(c, L, L.faces[fi], L.faces[fi].L, L.W);
     std::vector<double> D(L.n), al(L.n);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L.n; ++i) {
         double sr = 0.0;
         for (int fi : L.cf[i]) sr += L.faces[fi].S * rf[fi];
@@ -402,8 +413,8 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
     };
     std::vector<int> order(L.n);
     for (int i = 0; i < L.n; ++i) order[pos[i]] = i;
-    double s[5];
     if (sequential) {
+        double s[5];
         for (int k = 0; k < L.n; ++k) {
             int i = order[k];
             offdiag(i, true, s);
@@ -415,19 +426,26 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
             for (int q = 0; q < nv; ++q) L.dW[i * nv + q] -= 0.5 * al[i] * s[q] / D[i];
         }
     } else {
+        /* Cells of one colour never share a face, so each colour's loop is
+         * order-independent (Sec. 4.1). */
         for (int col = 1; col <= L.ncolor; ++col)
+#pragma omp parallel for schedule(static)
             for (int i = 0; i < L.n; ++i) {
                 if (L.color[i] != col) continue;
+                double s[5];
                 offdiag(i, true, s);
                 for (int q = 0; q < nv; ++q) L.dW[i * nv + q] = (rhs[i * nv + q] - 0.5 * al[i] * s[q]) / D[i];
             }
         for (int col = L.ncolor; col >= 1; --col)
+#pragma omp parallel for schedule(static)
             for (int i = 0; i < L.n; ++i) {
                 if (L.color[i] != col) continue;
+                double s[5];
                 offdiag(i, false, s);
                 for (int q = 0; q < nv; ++q) L.dW[i * nv + q] -= 0.5 * al[i] * s[q] / D[i];
             }
     }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < L.n; ++i) {
         const double th = update_fraction(p, &L.W[i * nv], &L.dW[i * nv]);
         if (th > 0.0)
@@ -473,6 +491,7 @@ int fine_step(orc_ctx* c, double* norm_out = nullptr, std::vector<double>* W_in 
         for (size_t k = 0; k < R.size(); ++k) (*res_out)[k] = -R[k];
     }
     bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
     for (int i = 0; i < L0.n; ++i) {
         double dW[5];
         for (int q = 0; q < nv; ++q) {
@@ -499,6 +518,7 @@ void restrict_level(orc_ctx* c, int l, const std::vector<double>& res_fine,
     Level& F = c->lv[l];
     Level& G = c->lv[l + 1];
     const std::vector<double>& Wf = W_fine ? *W_fine : F.W;
+#pragma omp parallel for schedule(static)
     for (int I = 0; I < G.n; ++I) {
         double w[5] = {0, 0, 0, 0, 0}, r[5] = {0, 0, 0, 0, 0}, amin = 1e300;
         for (int i : G.children[I]) {
@@ -526,6 +546,8 @@ void prolong_level(orc_ctx* c, int l) {
     const int nv = c->nvar;
     Level& F = c->lv[l];
     const Level& G = c->lv[l + 1];
+    long long skips = 0;
+#pragma omp parallel for schedule(static) reduction(+ : skips)
     for (int i = 0; i < F.n; ++i) {
         int I = F.parent[i];
         double a = c->p.df_prolong ? F.alpha[i] : 1.0;
@@ -534,8 +556,9 @@ void prolong_level(orc_ctx* c, int l) {
         const double th = update_fraction(c->p, &F.W[i * nv], dW);
         if (th > 0.0)
             for (int q = 0; q < nv; ++q) F.W[i * nv + q] += th * dW[q];
-        if (th < 1.0) ++c->prolong_skips;
+        if (th < 1.0) ++skips;
     }
+    c->prolong_skips += skips;
 }
 
 void freestream(const orc_params& p, double* W) {
