@@ -112,6 +112,10 @@ int orc_ghost(const orc_params* p, int tag, const double* W, const double* g, co
               double* Wg, double* gg);
 int orc_recon_eval(orc_ctx* c, int cell, const double* x, double* Wx, double* gx,
                    double* p2x, double* p1x, double* w_large);
+/* Per component of one fine cell's reconstruction (Sec. 3): the smoothness
+ * indicators of p^2 and p^1, the DF-scaled Green-Gauss gradient of p^1
+ * ([nvar][dim]) and the nonlinear weight of the large stencil. */
+int orc_recon_indicators(orc_ctx* c, int cell, double* beta0, double* beta1, double* g1, double* w_large);
 
 #ifdef __cplusplus
 }

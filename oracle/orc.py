@@ -250,6 +250,14 @@ class Oracle:
         self._chk(lib().orc_recon_eval(self.ctx, cell, _dp(xx), _dp(W), _dp(g), _dp(p2), _dp(p1), _dp(w)))
         return W, g, p2, p1, w
 
+    def recon_indicators(self, cell):
+        """beta_0, beta_1, the DF-scaled Green-Gauss gradient [nvar, dim] and the
+        large-stencil weight of one cell's reconstruction (Sec. 3)."""
+        nv = self.nvar
+        b0, b1, g1, w = np.zeros(nv), np.zeros(nv), np.zeros((nv, self.dim)), np.zeros(nv)
+        self._chk(lib().orc_recon_indicators(self.ctx, cell, _dp(b0), _dp(b1), _dp(g1), _dp(w)))
+        return b0, b1, g1, w
+
 
 # point functions ------------------------------------------------------------
 

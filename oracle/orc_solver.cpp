@@ -22,6 +22,7 @@ struct CellRec {
     double a[5][9];   /* p^2 coefficients (Sec. 3.1) */
     double g[5][3];   /* p^1 gradient (Sec. 3.2, alpha-scaled) */
     double w0[5], w1[5];
+    double b0[5], b1[5]; /* smoothness indicators beta_0 (p^2) and beta_1 (p^1) */
     bool guard;       /* positivity fallback to the constant state */
 };
 
@@ -188,6 +189,8 @@ void build_rec(orc_ctx* c, int i, CellRec& r) {
         double g2 = 0.0;
         for (int d = 0; d < dim; ++d) g2 += r.g[q][d] * r.g[q][d];
         double beta1 = std::pow(V, 2.0 / dim) * g2;
+        r.b0[q] = beta0;
+        r.b1[q] = beta1;
         const double gl = c->p.weno_gamma_large, gs = 1.0 - gl, eps = c->p.weno_eps;
         double tz = std::fabs(beta0 - beta1);
         double t0 = tz / (beta0 + eps), t1 = tz / (beta1 + eps);
@@ -878,6 +881,22 @@ int orc_recon_eval(orc_ctx* c, int cell, const double* x, double* Wx, double* gx
         if (p2x) p2x[q] = p2;
         if (p1x) p1x[q] = p1;
         if (w_large) w_large[q] = r.w0[q];
+    }
+    return ORC_OK;
+}
+
+int orc_recon_indicators(orc_ctx* c, int cell, double* beta0, double* beta1, double* g1, double* w_large) {
+    int rc = check(c, 0);
+    if (rc) return rc;
+    if (cell < 0 || cell >= c->lv[0].n) return ORC_EINVAL;
+    CellRec r;
+    build_rec(c, cell, r);
+    for (int q = 0; q < c->nvar; ++q) {
+        if (beta0) beta0[q] = r.b0[q];
+        if (beta1) beta1[q] = r.b1[q];
+        if (w_large) w_large[q] = r.w0[q];
+        if (g1)
+            for (int d = 0; d < c->dim; ++d) g1[q * c->dim + d] = r.g[q][d];
     }
     return ORC_OK;
 }
