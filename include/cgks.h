@@ -56,6 +56,7 @@ extern "C" {
 #define CGKS_EMESH (-2)    /* invalid mesh: non-positive volume, non-manifold face, untagged boundary */
 #define CGKS_EDEVICE (-3)  /* HIP runtime error; the message carries the hipError_t text */
 #define CGKS_ENONPHYS (-4) /* NaN, rho <= 0 or p <= 0 after a cycle; state rolled back */
+#define CGKS_ELIMIT (-5)   /* size beyond the fixed workspace of an entry point that allocates nothing */
 
 #define CGKS_HOST 0        /* pointer arguments are host memory */
 #define CGKS_DEVICE 1      /* pointer arguments are device memory of the context's device */
@@ -305,6 +306,19 @@ int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n);
 /* Loss mean_n sum_k (out - Y)^2 (host float) and, if grads_out is not NULL,
  * its gradient in the flat host layout; the weights are not changed. */
 int cgks_mlp_grads(cgks_mlp* m, const float* X, const float* Y, int n, float* grads_out, float* loss);
+/* cgks_mlp_forward for callers that cannot allocate device memory (code under
+ * stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same outputs, bit for bit, but the
+ * hidden activations live in a fixed file-scope device array of the library
+ * (17.8 MB per device, held until the process ends) instead of the network's
+ * growable workspace, and Y is written directly.  It calls no hipMalloc,
+ * hipFree or allocating routine.  X [n][5] and Y [n][4] are device float
+ * pointers of the caller; n <= CGKS_MLP_NOALLOC_MAX_ROWS, else CGKS_ELIMIT
+ * and nothing runs.  Every call on one device shares that array: calls that
+ * overlap on one device (other host threads, other streams) race, and must
+ * be serialised by the caller.  Synchronises the network's stream. */
+#define CGKS_MLP_NOALLOC_MAX_ROWS 16384
+int cgks_mlp_forward_noalloc(cgks_mlp* m, const float* X, float* Y, int n);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
  * batch; loss (host, may be NULL) is the loss before the step. */
 int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, float lr, float* loss);

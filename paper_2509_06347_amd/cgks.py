@@ -20,7 +20,7 @@ if not os.path.exists(LIBPATH):
 
 _lib = C.CDLL(LIBPATH)
 
-OK, NOTCONV, EINVAL, EMESH, EDEVICE, ENONPHYS = 0, 1, -1, -2, -3, -4
+OK, NOTCONV, EINVAL, EMESH, EDEVICE, ENONPHYS, ELIMIT = 0, 1, -1, -2, -3, -4, -5
 HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 TAG_FARFIELD, TAG_SLIP, TAG_ISOTHERMAL, TAG_ADIABATIC = 1, 2, 3, 4
@@ -94,6 +94,7 @@ _sigs = {
     "cgks_mlp_get_weights": (C.c_int, [_P, _P]),
     "cgks_mlp_set_weights": (C.c_int, [_P, _P]),
     "cgks_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int]),
+    "cgks_mlp_forward_noalloc": (C.c_int, [_P, _P, _P, C.c_int]),
     "cgks_mlp_grads": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
     "cgks_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
     "cgks_init_from_mlp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.POINTER(C.c_int)]),
@@ -371,6 +372,7 @@ class MLP:
     float32 device tensors of shape [n, 5] and [n, 4]."""
 
     SIZES = (5, 256, 256, 256, 4)
+    NOALLOC_MAX_ROWS = 16384
 
     def __init__(self, seed=0, stream=None):
         h = _P()
@@ -412,6 +414,16 @@ class MLP:
         if ny != n:
             raise ValueError("X and Y differ in rows")
         self._check(_lib.cgks_mlp_forward(self.h, px, py, n), "cgks_mlp_forward")
+
+    def forward_noalloc(self, X, Y):
+        """cgks_mlp_forward_noalloc: the forward pass in the library's fixed
+        workspace (at most NOALLOC_MAX_ROWS rows; calls on one device must not
+        overlap)."""
+        px, n = self._dev(X, 5)
+        py, ny = self._dev(Y, 4)
+        if ny != n:
+            raise ValueError("X and Y differ in rows")
+        self._check(_lib.cgks_mlp_forward_noalloc(self.h, px, py, n), "cgks_mlp_forward_noalloc")
 
     def grads(self, X, Y):
         px, n = self._dev(X, 5)

@@ -474,6 +474,7 @@ const char* cgks_strerror(int code) {
         case CGKS_EMESH: return "invalid mesh";
         case CGKS_EDEVICE: return "HIP device error";
         case CGKS_ENONPHYS: return "non-physical state";
+        case CGKS_ELIMIT: return "size beyond a fixed workspace limit";
         default: return "unknown error";
     }
 }

@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -35,7 +36,7 @@ constexpr int DOUT[NL] = {256, 256, 256, 4};
 constexpr int KPAD[NL] = {32, 256, 256, 256};          /* padded input width */
 constexpr int NPAD[NL] = {256, 256, 256, 16};          /* padded output width */
 
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3, EPI_BIAS_SILU_NOZ = 4 };
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu_f(float z) {
@@ -46,6 +47,7 @@ __device__ __forceinline__ float dsilu_f(float z) {
 /*
  * C = A B (+ epilogue).  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
  * EPI_BIAS_SILU: Z = C + bias[n] -> Cz (fp32) and Cb = bf16(silu(Z)).
+ * EPI_BIAS_SILU_NOZ: Cb = bf16(silu(C + bias[n])) only (inference).
  * EPI_BIAS:      C + bias[n] -> C (fp32).
  * EPI_DSILU:     Cb = bf16(C * silu'(Zin[m, n]))  (backward through SiLU).
  * EPI_STORE:     C -> C (fp32).
@@ -109,6 +111,8 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const __bf16*
                     v += bias[n];
                     Cz[(long)m * ldc + n] = v;
                     Cb[(long)m * ldb + n] = (__bf16)silu_f(v);
+                } else if (EPI == EPI_BIAS_SILU_NOZ) {
+                    Cb[(long)m * ldb + n] = (__bf16)silu_f(v + bias[n]);
                 } else if (EPI == EPI_BIAS) {
                     Cz[(long)m * ldc + n] = v + bias[n];
                 } else if (EPI == EPI_DSILU) {
@@ -230,6 +234,40 @@ __global__ void k_mlp_state(const float* out, const float* tt, double mach, doub
 }
 
 inline int nb(long m, int b) { return (int)((m + b - 1) / b); }
+
+/* Fixed workspace of cgks_mlp_forward_noalloc: for CGKS_MLP_NOALLOC_MAX_ROWS
+ * rows, the packed input (32 bf16 per row) then two ping-pong hidden layers
+ * (256 bf16 per row each); 17.8 MB per device, held until the process ends. */
+constexpr size_t NOALLOC_H0 = 0;
+constexpr size_t NOALLOC_HA = (size_t)CGKS_MLP_NOALLOC_MAX_ROWS * 32;
+constexpr size_t NOALLOC_HB = NOALLOC_HA + (size_t)CGKS_MLP_NOALLOC_MAX_ROWS * 256;
+constexpr size_t NOALLOC_ELEMS = NOALLOC_HB + (size_t)CGKS_MLP_NOALLOC_MAX_ROWS * 256;
+
+}  // namespace
+
+static __device__ __align__(256) __bf16 scratch[NOALLOC_ELEMS];
+
+namespace {
+
+/* Device address of `scratch` on the current device.  In host code the
+ * array's name is only a host-side stand-in, so kernels are given this
+ * address, looked up once per device. */
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+__bf16* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(__bf16** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return CGKS_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CGKS_EDEVICE;
+        g_scratch_ptr[dev] = (__bf16*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CGKS_OK;
+}
 
 }  // namespace
 
@@ -363,7 +401,8 @@ int cgks_mlp_create(cgks_mlp** out, int seed) {
         ok &= mal(m, &m->Wb[l], nw) == hipSuccess;
         if (ok) k_to_bf16<<<nb(nw, 256), 256>>>(m->P[l][0], m->Wb[l], (int)nw);
     }
-    if (!ok || hipDeviceSynchronize() != hipSuccess) {
+    __bf16* ws = nullptr;
+    if (!ok || hipDeviceSynchronize() != hipSuccess || scratch_address(&ws) != CGKS_OK) {
         cgks_mlp_destroy(m);
         return CGKS_EDEVICE;
     }
@@ -436,6 +475,32 @@ int cgks_mlp_forward(cgks_mlp* m, const float* X, float* Y, int n) {
                          hipMemcpyDeviceToDevice, m->stream) != hipSuccess)
         return CGKS_EDEVICE;
     return hipStreamSynchronize(m->stream) == hipSuccess ? CGKS_OK : CGKS_EDEVICE;
+}
+
+int cgks_mlp_forward_noalloc(cgks_mlp* m, const float* X, float* Y, int n) {
+    if (!m || n < 0 || n > CGKS_MLP_NOALLOC_MAX_ROWS) return n > CGKS_MLP_NOALLOC_MAX_ROWS ? CGKS_ELIMIT : CGKS_EINVAL;
+    if (n == 0) return CGKS_OK;
+    if (!X || !Y) return CGKS_EINVAL;
+    __bf16* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    __bf16* H0 = ws + NOALLOC_H0;
+    __bf16* Hs[2] = {ws + NOALLOC_HA, ws + NOALLOC_HB};
+    hipStream_t st = m->stream;
+    /* the same kernels and arithmetic as cgks_mlp_forward; hidden layers
+     * alternate between the two halves, the last layer writes Y directly */
+    k_pack_input<<<nb((long)n * 32, 256), 256, 0, st>>>(X, H0, n);
+    for (int l = 0; l < NL; ++l) {
+        const __bf16* in = l == 0 ? H0 : Hs[(l - 1) & 1];
+        if (l < NL - 1)
+            gemm<EPI_BIAS_SILU_NOZ>(st, n, DOUT[l], KPAD[l], in, KPAD[l], 1, m->Wb[l], 1, KPAD[l], nullptr, 0,
+                                    Hs[l & 1], KPAD[l + 1], m->P[l][1], nullptr, 0);
+        else
+            gemm<EPI_BIAS>(st, n, DOUT[l], KPAD[l], in, KPAD[l], 1, m->Wb[l], 1, KPAD[l], Y, 4, nullptr, 0,
+                           m->P[l][1], nullptr, 0);
+    }
+    if (hipGetLastError() != hipSuccess) return CGKS_EDEVICE;
+    return hipStreamSynchronize(st) == hipSuccess ? CGKS_OK : CGKS_EDEVICE;
 }
 
 int cgks_mlp_grads(cgks_mlp* m, const float* X, const float* Y, int n, float* grads_out, float* loss) {
