@@ -1,26 +1,35 @@
 """Benchmark of the multigrid CGKS V-cycle on one MI355X.
 
-Workload (default): the viscous Mach 8 cylinder, Re = 1e4 per diameter,
-Pr = 0.72, gamma = 1.4, isothermal wall T_w/T_inf = 1; 128 x 32 coarsest
-annulus quads (radial stretching 1.2, seeded +-0.1h node jitter) split into
-triangles and refined twice -> 131,072 fine triangles on 3 nested levels.
+Workload (default): the largest single-GPU configuration, the inviscid Mach 6
+flow around a unit-diameter sphere on a spherical shell r in [0.5, 6]: the
+Kuhn triangulation of a 32 x 16 x 16 (azimuth x polar x radial) grid with
+geometric radial stretching 1.2, refined twice by Freudenthal subdivision ->
+3,096,576 fine tetrahedra (after removing the polar-degenerate ones) on three
+nested levels (393,216 and 49,152 agglomerates), slip wall, far field.  The
+cycles start impulsively from the free stream with a 10-cycle implicit-CFL
+ramp.  `--workload cylinder_ns_mach8_131k` runs the 2-D viscous Mach 8
+cylinder (131,072 triangles) instead.
 
 A "step" is one full 3-level V-cycle (fine residual, explicit fine step,
 second fine residual, restriction, 6 multi-colour LU-SGS iterations on each
-coarse level, DF-limited prolongation).  Inputs are resident in HBM before
-the timed region; K V-cycles are replayed from a captured hipGraph between
-two events on the solver's stream.
+coarse level, DF-limited prolongation) in FP64.  Inputs are resident in HBM
+before the timed region; K V-cycles are replayed from a captured hipGraph
+between two events on the solver's stream (torch's current stream).
 
 Printed: one JSON line with the metric (Mcell * V-cycles / s), the roofline
-of the dominant kernel (the Gauss-point BGK flux, FP64-ALU bound, timed with
-HIP events on the solver's stream) and the CPU oracle timed on one V-cycle of
-the same workload as a baseline.
+of the dominant kernel (the fine reconstruction, HBM-bound, timed with HIP
+events on the solver's stream; algorithmic bytes per cell below), the other
+fine kernels' times, the FP32-coarse-correction form on the same workload,
+time-to-1e-10 on the one steady case that converges (outside the configs
+this benchmark is quoted on) and the CPU oracle's rate on bounded samples of
+the same workload family, on one core and on all cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,65 +37,71 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mcell·V-cycles/s and time-to-1e-10 residual, plain FP64 vs chosen form"
-
-# Algorithmic FP64 operations of one Gauss-point evaluation of the 2-D BGK
-# flux kernel (k_flux): +,-,*,/, sqrt and each transcendental counted as one
-# operation, counted by running the kernel's own source on a counting number
-# type (csrc/flop_count.cpp).  Navier-Stokes branch (heat-flux fix) on.
-FLUX_FLOPS_PER_GP_NS = 4983
-FLUX_FLOPS_PER_GP_EULER = 4948
-MI355X_FP64_VECTOR_TFLOPS = 78.6
 MI355X_HBM_GBS = 8000.0
+MI355X_FP64_VECTOR_TFLOPS = 78.6
 
-# Algorithmic HBM bytes of the 2-D reconstruction per fine cell: what its data
-# layout must move at least once per launch.  Reads: W 4, slopes 8, V/h/alpha 3,
-# slot areas 3, normals 6, Gauss-point offsets 12, basis means 5, operator 45
-# doubles, slot neighbours and tags 6 ints; writes: 2 x 3 x 12 Gauss-point
-# states and 2 time steps (doubles).
-RECON_BYTES_PER_CELL_2D = 8 * (4 + 8 + 3 + 3 + 6 + 12 + 5 + 45) + 4 * 6 + 8 * (72 + 2)
+# Algorithmic HBM bytes per fine cell of one reconstruction launch: every input
+# it needs, read once (the neighbours' states are other cells' own states), and
+# the smallest hand-off to the flux kernel, the reconstructed polynomial of each
+# component (p^2 part and DF-scaled Green-Gauss part: NV x (NQ + D) doubles),
+# plus the two local time steps.  Not counted: any larger intermediate the
+# kernels happen to write.
+#   3-D inputs (doubles): W 5, slopes 15, alpha 1, V 1, h 1, slot areas 4,
+#   normals 12, basis means 9, operator 9 x 16 = 144, Gauss-point offsets
+#   4 x 3 x 3 = 36; neighbour ids and tags 8 int32.  Output 5 x 12 + 2.
+#   2-D: W 4, slopes 8, alpha/V/h 3, areas 3, normals 6, means 5, operator
+#   5 x 9 = 45, offsets 3 x 2 x 2 = 12; 6 int32.  Output 4 x 7 + 2.
+RECON_BYTES_PER_CELL = {
+    3: 8 * (5 + 15 + 1 + 1 + 1 + 4 + 12 + 9 + 144 + 36) + 4 * 8 + 8 * (5 * 12 + 2),
+    2: 8 * (4 + 8 + 3 + 3 + 6 + 5 + 45 + 12) + 4 * 6 + 8 * (4 * 7 + 2),
+}
 
 # HBM bytes moved by one launch of a kernel on a workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE counter runs of this script scaled by the counters'
-# reading for a plain copy of known size (FETCH x2.0, WRITE x1.0).  Valid only
-# for the kernel source the counters were taken with; absent when not taken.
-TRAFFIC_BYTES = {("cylinder_ns_mach8_131k", "k_recon2"): 180.8e6,
-                 ("cylinder_ns_mach8_131k", "k_flux"): 149.4e6}
+# FETCH_SIZE and WRITE_SIZE counter runs of this script, each scaled by the
+# counter's reading for a plain device copy of known size.  Valid only for the
+# kernel source the counters were taken with; absent (null) otherwise.
+TRAFFIC_BYTES = {}
 
 
 def workload(name):
     import synthmesh as sm
+    if name == "sphere_euler_mach6_3.1M":
+        return sm.sphere_shell_kuhn(32, 16, 16, nref=2), dict(mach=6.0, cfl_ramp=10)
+    if name == "sphere_euler_mach6_46k":
+        return sm.sphere_shell_kuhn(8, 4, 4, nref=2), dict(mach=6.0, cfl_ramp=10)
     if name == "cylinder_ns_mach8_131k":
         return sm.cylinder_ns_large(), dict(mach=8.0, reynolds=1e4, prandtl=0.72, wall_T_ratio=1.0)
-    if name == "cylinder_euler_mach038_8k":
-        return sm.cylinder_euler_small(), dict(mach=0.38)
     raise SystemExit(f"unknown workload {name}")
 
 
-# The chosen form of the V-cycle for time-to-tolerance: FP32 coarse correction
-# and a smoothing schedule tuned on the steady Re 40 cylinder (same fixed point
-# as the plain form, which keeps one fine step and six coarse iterations).
-CHOSEN_FORM = dict(precision=1, n_pre_fine=3, slope_relax=0.15, n_sweeps=3)
+def initial_state(solver, mesh, params):
+    """Free stream; at a no-slip wall the velocity is ramped to zero."""
+    import numpy as np
+    solver.init_freestream()
+    W, _, _ = solver.get_state()
+    if params.get("reynolds", 0.0) > 0.0:
+        V, C = solver.cell_geometry(0)
+        r = np.tanh((np.hypot(C[:, 0], C[:, 1]) - 0.5) / 0.3)
+        W[:, 1] *= r
+        W[:, 2] *= r
+        W[:, 3] = (1.0 / 1.4) / 0.4 + 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0]
+        solver.set_state(W)
+    return W
 
 
-def time_to_tol(cgks, mesh, params, tol, max_cycles, **form):
-    """Wall time from the free-stream initialisation to the first cycle with
-    norm <= tol (solver set-up excluded, initialisation included)."""
+def timed_cycles(solver, stream, steps):
     import torch
-    s = cgks.Solver(mesh, n_levels=3, **params, **form)
-    if form:
-        s.init_freestream()
-        s.autotune()
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    s.init_freestream()
-    rc, hist = s.solve(tol=tol, max_cycles=max_cycles)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    hist = solver.run_cycles(steps)
+    e1.record(stream)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    W, _, _ = s.get_state()
-    return {"seconds": dt if rc == cgks.OK else None, "cycles": int(len(hist)),
-            "final_norm": float(hist[-1]) if len(hist) else None, "converged": rc == cgks.OK,
-            "ladder": ladder(hist, dt)}, W
+    return e0.elapsed_time(e1), hist
 
+
+# ------------------------------------------------------------ time to 1e-10 --
 
 LADDER = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
 
@@ -105,62 +120,131 @@ def ladder(hist, seconds):
     return out
 
 
-def explicit_solve(cgks, mesh, params, cap):
-    """The explicit CGKS solver: the fine step alone (one level), from the free
-    stream, until 1e-10 or cap steps."""
+def time_to_tol(cgks, mesh, params, tol, max_cycles, n_levels=3, **form):
+    """Wall time from the free-stream initialisation to the first cycle with
+    norm <= tol (set-up and autotuning excluded, initialisation included)."""
     import torch
-    s = cgks.Solver(mesh, n_levels=1, **params)
+    s = cgks.Solver(mesh, n_levels=n_levels, **params, **form)
     s.init_freestream()
     s.autotune()
     torch.cuda.synchronize()
     t = time.perf_counter()
     s.init_freestream()
-    rc, hist = s.solve(tol=1e-10, max_cycles=cap)
+    rc, hist = s.solve(tol=tol, max_cycles=max_cycles)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    return {"steps": int(len(hist)), "seconds": dt, "converged": rc == cgks.OK,
-            "final_norm": float(hist[-1]), "min_norm": float(hist.min()), "ladder": ladder(hist, dt)}
+    W, _, _ = s.get_state()
+    return {"seconds": dt if rc == cgks.OK else None, "cycles": int(len(hist)), "converged": rc == cgks.OK,
+            "final_norm": float(hist[-1]) if len(hist) else None, "min_norm": float(hist.min()),
+            "ladder": ladder(hist, dt)}, W
 
 
-def initial_state(solver, mesh, params):
-    """Free stream, with the velocity ramped to zero at a no-slip wall."""
+# The tuned smoothing schedule: three fine steps per cycle with slope relaxation
+# 0.15 and three LU-SGS iterations per coarse level (same fixed point).
+TUNED = dict(n_pre_fine=3, slope_relax=0.15, n_sweeps=3)
+
+
+def time_to_1e10(cgks, max_cycles, explicit_cap):
+    """Plain FP64 against the FP32 coarse correction, with the paper's schedule
+    and with the tuned one, all autotuned, on the steady Re 40 cylinder."""
     import numpy as np
-    solver.init_freestream()
-    if params.get("reynolds", 0.0) > 0.0:
-        W, _, _ = solver.get_state()
-        V, C = solver.cell_geometry(0)
-        r = np.tanh((np.hypot(C[:, 0], C[:, 1]) - 0.5) / 0.3)
-        W[:, 1] *= r
-        W[:, 2] *= r
-        W[:, 3] = (1.0 / 1.4) / 0.4 + 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0]
-        solver.set_state(W)
-        return W
-    W, _, _ = solver.get_state()
-    return W
+    import synthmesh as sm
+    mesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=2, wall_tag=sm.ISOTHERMAL)
+    prm = dict(mach=0.15, reynolds=40.0)
+    rows = {}
+    fields = {}
+    for name, form in (("plain_fp64", {}), ("fp32_correction", dict(precision=cgks.MIXED)),
+                       ("tuned_schedule_fp64", dict(TUNED)),
+                       ("tuned_schedule_fp32_correction", dict(TUNED, precision=cgks.MIXED))):
+        rows[name], fields[name] = time_to_tol(cgks, mesh, prm, 1e-10, max_cycles, **form)
+    ref = fields["plain_fp64"]
+    for name in rows:
+        if name != "plain_fp64":
+            rows[name]["field_diff_vs_plain_fp64"] = float(np.abs(fields[name] - ref).max() / np.abs(ref).max())
+    out = {"workload": "cylinder_ns_mach015_re40_8k (steady; not one of the configurations this benchmark "
+                       "is quoted on: none of those reaches 1e-10)",
+           "fine_cells": mesh.n_cells, "tol": 1e-10, "forms": rows,
+           "tuned_schedule": "3 fine steps per cycle with slope relaxation 0.15, 3 LU-SGS iterations per coarse level"}
+    if explicit_cap > 0:
+        ex, _ = time_to_tol(cgks, mesh, prm, 1e-10, explicit_cap, n_levels=1)
+        speed = {L: ex["ladder"][L]["seconds"] / rows["plain_fp64"]["ladder"][L]["seconds"]
+                 for L in ex["ladder"] if L in rows["plain_fp64"]["ladder"]}
+        out["gmg_vs_explicit"] = {"explicit": ex, "speedup_plain_fp64": speed,
+                                  "note": "explicit = the fine CGKS step alone (one level) from the free stream"}
+    return out
 
 
-def cpu_baseline(mesh, params, W0, n_fine):
-    """The CPU oracle (single thread, as it stands) on one V-cycle of the same workload."""
+# --------------------------------------------------------------- CPU oracle --
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_rate(mesh, params, threads, reps=3):
+    """Median over reps of one oracle V-cycle from the free stream (set-up excluded)."""
+    import numpy as np
     from oracle import orc
+    orc.set_threads(threads)
     o = orc.Oracle(mesh, n_levels=3, **params)
-    o.set_state(W0)
-    t = time.perf_counter()
-    o.vcycle()
-    dt = time.perf_counter() - t
-    return {"value": n_fine / dt / 1e6, "unit": "Mcell·V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 V-cycle of the same {n_fine}-cell workload from the same initial state, "
-                      f"{dt:.1f} s single-threaded"}
+    times = []
+    for _ in range(reps):
+        o.init_freestream()
+        t = time.perf_counter()
+        o.vcycle()
+        times.append(time.perf_counter() - t)
+    med = float(np.median(times))
+    return {"value": mesh.n_cells / med / 1e6, "seconds_per_cycle": med, "runs_s": times, "threads": threads}
 
+
+def cpu_baseline(workload_name, params):
+    """The oracle (plain FP64 C++, OpenMP loops with results independent of the
+    thread count) on bounded samples of the same workload family: one V-cycle,
+    median of 3, on all host cores and on one core."""
+    import synthmesh as sm
+    if workload_name.startswith("sphere"):
+        big, small = sm.sphere_shell_kuhn(8, 4, 4, nref=2), sm.sphere_shell_kuhn(4, 2, 2, nref=2)
+        fam = "Kuhn sphere shell, Mach 6 Euler"
+    else:
+        big, small = sm.annulus(32, 8, jitter=0.10, seed=1, nref=2, wall_tag=sm.ISOTHERMAL), \
+            sm.annulus(16, 4, jitter=0.10, seed=1, nref=2, wall_tag=sm.ISOTHERMAL)
+        fam = "annulus, Mach 8 Navier-Stokes"
+    ncores = host_cores()
+    allc = oracle_rate(big, params, ncores)
+    one = oracle_rate(small, params, 1)
+    return {"value": allc["value"], "unit": "Mcell·V-cycles/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{fam}: one V-cycle from the free stream on {big.n_cells} cells with {ncores} threads "
+                      f"(median of 3: {allc['seconds_per_cycle']:.2f} s), and on {small.n_cells} cells with "
+                      f"1 thread (median of 3: {one['seconds_per_cycle']:.2f} s)",
+            "one_core": {"value": one["value"], "cells": small.n_cells, "runs_s": one["runs_s"]},
+            "all_cores": {"value": allc["value"], "cells": big.n_cells, "runs_s": allc["runs_s"]},
+            "cpu_model": cpu_model()}
+
+
+# --------------------------------------------------------------------- main --
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cylinder_ns_mach8_131k")
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="sphere_euler_mach6_3.1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttol", action="store_true", help="skip the time-to-1e-10 comparison")
     ap.add_argument("--max-cycles", type=int, default=12000)
-    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--explicit-cap", type=int, default=100000,
                     help="most steps of the explicit-solver comparison (0 skips it)")
     args = ap.parse_args()
@@ -169,13 +253,13 @@ def main():
               "a sharded multi-GPU path is not part of this library", file=sys.stderr)
         raise SystemExit(2)
 
-    import numpy as np
     import torch
 
     from paper_2509_06347_amd import cgks
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
     mesh, params = workload(args.workload)
     stream = torch.cuda.current_stream()
     solver = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, **params)
@@ -185,75 +269,43 @@ def main():
     if args.warmup > 0:
         solver.run_cycles(args.warmup)
     shapes = solver.autotune()        # launch shapes only; the arithmetic is unchanged
+    solver.set_state(W0)              # restart the ramp: the timed cycles follow the warm-up
     if args.warmup > 0:
         solver.run_cycles(args.warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    hist = solver.run_cycles(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms, hist = timed_cycles(solver, stream, args.steps)
     ms_per_step = ms / args.steps
     value = n_fine * args.steps / (ms / 1e3) / 1e6
+    print(f"bench: {ms_per_step:.3f} ms per V-cycle", file=sys.stderr, flush=True)
 
-    # dominant kernel (largest share of the cycle per launch): the reconstruction,
-    # HBM-bound; the Gauss-point flux (FP64-ALU-bound) is reported beside it.
-    # Both timed with HIP events on the solver's stream.
-    rec_ms, n_cell = solver.time_kernel(0, args.kernel_reps)
-    rec_bytes = RECON_BYTES_PER_CELL_2D * n_cell
-    rec_gbs = rec_bytes / (rec_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_recon2<2>", "achieved": rec_gbs, "peak": MI355X_HBM_GBS,
-            "unit": "GB/s", "frac": rec_gbs / MI355X_HBM_GBS,
-            "traffic": TRAFFIC_BYTES.get((args.workload, "k_recon2")),
-            "avg_ms": rec_ms, "work_items": n_cell, "bytes_per_item": RECON_BYTES_PER_CELL_2D}
-    flux_ms, n_gp = solver.time_kernel(1, args.kernel_reps)
-    fpg = FLUX_FLOPS_PER_GP_NS if params.get("reynolds", 0.0) > 0 else FLUX_FLOPS_PER_GP_EULER
-    achieved = fpg * n_gp / (flux_ms / 1e3) / 1e12
-    roof_flux = {"bound": "alu", "kernel": "k_flux<2>", "achieved": achieved,
-                 "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                 "frac": achieved / MI355X_FP64_VECTOR_TFLOPS,
-                 "traffic": TRAFFIC_BYTES.get((args.workload, "k_flux")),
-                 "avg_ms": flux_ms, "work_items": n_gp, "flops_per_item": fpg}
+    # fine kernels, each timed with HIP events on the solver's stream inside
+    # full fine residuals; the reconstruction is the dominant one
+    kern = {}
+    for k, name in enumerate(("recon", "flux", "gather")):
+        avg, items = solver.time_kernel(k, args.kernel_reps)
+        kern[name] = {"avg_ms": avg, "work_items": items,
+                      "unit": "face Gauss points" if k == 1 else "fine cells"}
+    d = mesh.dim
+    rb = RECON_BYTES_PER_CELL[d]
+    rec = kern["recon"]
+    gbs = rb * rec["work_items"] / (rec["avg_ms"] / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": f"k_recon2<{d}>", "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, "k_recon2")),
+            "avg_ms": rec["avg_ms"], "work_items": rec["work_items"], "bytes_per_item": rb}
 
-    # chosen form: FP32 coarse correction inside the FP64 defect correction
+    # the FP32 coarse correction on the same workload and start
     mixed = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, precision=cgks.MIXED, **params)
     mixed.set_state(W0)
     if args.warmup > 0:
         mixed.run_cycles(args.warmup)
     mixed.autotune()
-    torch.cuda.synchronize()
-    e0.record(stream)
-    mixed.run_cycles(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    mms = e0.elapsed_time(e1)
+    mixed.set_state(W0)
+    if args.warmup > 0:
+        mixed.run_cycles(args.warmup)
+    mms, mhist = timed_cycles(mixed, stream, args.steps)
     chosen = {"form": "FP64 residual, FP32 coarse correction, autotuned launch shapes",
-              "value": n_fine * args.steps / (mms / 1e3) / 1e6, "ms_per_step": mms / args.steps}
-
-    # time to 1e-10: the benchmark workload (a Re 1e4 wake) has no steady state the
-    # cycles converge to, so the time is measured on the steady Re 40 cylinder
-    import synthmesh as sm
-    smesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=2, wall_tag=sm.ISOTHERMAL)
-    sparams = dict(mach=0.15, reynolds=40.0)
-    plain, Wp = time_to_tol(cgks, smesh, sparams, 1e-10, args.max_cycles)
-    chosen_t, Wc = time_to_tol(cgks, smesh, sparams, 1e-10, args.max_cycles, **CHOSEN_FORM)
-    chosen_t["form"] = ("FP32 coarse correction, 3 fine steps per cycle with slope relaxation 0.15, "
-                        "3 LU-SGS iterations per coarse level, autotuned launch shapes")
-    chosen_t["field_diff_vs_fp64"] = float(np.abs(Wc - Wp).max() / np.abs(Wp).max())
-    ttol = {"workload": "cylinder_ns_mach015_re40_8k", "fine_cells": smesh.n_cells, "tol": 1e-10,
-            "plain_fp64": plain, "chosen_form": chosen_t,
-            "note": "the benchmark workload's residual does not fall to 1e-10 (unsteady wake)"}
-    # multigrid against the explicit CGKS solver on the same case (the paper's
-    # speedup comparison), at every residual level both reach
-    if args.explicit_cap > 0:
-        ex = explicit_solve(cgks, smesh, sparams, args.explicit_cap)
-        speed = {L: {"plain_fp64": ex["ladder"][L]["seconds"] / plain["ladder"][L]["seconds"],
-                     "chosen_form": ex["ladder"][L]["seconds"] / chosen_t["ladder"][L]["seconds"]}
-                 for L in ex["ladder"] if L in plain["ladder"] and L in chosen_t["ladder"]}
-        ttol["gmg_vs_explicit"] = {"explicit": ex, "speedup": speed,
-                                   "note": "explicit = the fine CGKS step alone (one level) from the free stream"}
+              "value": n_fine * args.steps / (mms / 1e3) / 1e6, "ms_per_step": mms / args.steps,
+              "last_norm": float(mhist[-1])}
+    del mixed
 
     out = {"metric": METRIC, "value": value, "unit": "Mcell·V-cycles/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -261,12 +313,16 @@ def main():
            "data": "synthetic",
            "config": {"workload": args.workload, "fine_cells": n_fine, "levels": 3,
                       "sizes": solver.sizes, **params},
-           "roofline": roof, "roofline_flux": roof_flux, "launch_shapes": shapes,
+           "roofline": roof, "fine_kernels": kern, "launch_shapes": shapes,
            "chosen_form": chosen,
-           "time_to_1e-10": ttol,
            "last_norm": float(hist[-1]) if len(hist) else None}
+    del solver
+    if not args.no_ttol:
+        print("bench: time to 1e-10", file=sys.stderr, flush=True)
+        out["time_to_1e-10"] = time_to_1e10(cgks, args.max_cycles, args.explicit_cap)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, params, W0, n_fine)
+        print("bench: CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, params)
     print(json.dumps(out), flush=True)
 
 

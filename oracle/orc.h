@@ -100,6 +100,10 @@ int orc_prolong(orc_ctx* c, int level);
 int orc_vcycle(orc_ctx* c, double* norm_out);
 int orc_solve(orc_ctx* c, double tol, int max_cycles, int* cycles_out, double* history, int history_cap);
 int orc_stats(orc_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);
+/* OpenMP threads of the loops over faces, cells and same-colour cells (every
+ * result is bitwise the same for any count). */
+int orc_set_threads(int n);
+int orc_get_threads(void);
 
 /* Point-wise pieces, exported so that tests can pin them in isolation. */
 int orc_moments(double U, double lam, int range, int nmax, double* out);

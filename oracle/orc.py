@@ -64,6 +64,16 @@ def lib():
     return _LIB
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (results are bitwise independent of it)."""
+    if lib().orc_set_threads(int(n)) != 0:
+        raise ValueError("thread count must be >= 1")
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
+
+
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 

@@ -7,6 +7,8 @@
  */
 #include "orc_internal.h"
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -859,6 +861,15 @@ int orc_solve(orc_ctx* c, double tol, int max_cycles, int* cycles_out, double* h
     }
     return ORC_NOTCONV;
 }
+
+/* Threads of the OpenMP loops (results do not depend on it). */
+int orc_set_threads(int n) {
+    if (n < 1) return ORC_EINVAL;
+    omp_set_num_threads(n);
+    return ORC_OK;
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 int orc_stats(orc_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
     if (!c) return ORC_EINVAL;

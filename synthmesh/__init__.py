@@ -386,6 +386,126 @@ def sphere_shell(n_az, n_pol, n_rad, r_in=0.5, r_out=6.0, q=1.2, nref=2, jitter=
                      q=q, nref=nref, jitter=jitter, seed=seed))
 
 
+def _kuhn_tets(na, npol, nrad):
+    """Kuhn triangulation of the index grid [0, na) x [0, npol) x [0, nrad)
+    (azimuth periodic): cube (i, j, k) is cut into 6 tetrahedra along its
+    (0,0,0)-(1,1,1) diagonal, one per order in which the path from corner
+    (0,0,0) steps along the three axes (_KUHN).  Returns the cube origins
+    [n, 3] and the order ids [n] of all tetrahedra, order fastest."""
+    i, j, k = np.meshgrid(np.arange(na), np.arange(npol), np.arange(nrad), indexing="ij")
+    org = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
+    org = np.repeat(org, 6, axis=0)
+    perm = np.tile(np.arange(6), len(org) // 6)
+    return org, perm
+
+
+# Axis stepping order of each _KUHN tetrahedron (0 = azimuth, 1 = polar, 2 = radial).
+_KUHN_ORDER = np.array([(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)])
+
+
+def _kuhn_parent(org, perm):
+    """The Kuhn tetrahedron of the grid with half the resolution that contains
+    each given tetrahedron (Freudenthal refinement nests the two): the cube
+    and stepping order of the centroid, computed exactly in index units."""
+    c4 = 4 * org.astype(np.int64)                   # centroid x 4, integer
+    step = np.array([3, 2, 1])
+    for t in range(3):
+        c4[np.arange(len(org)), _KUHN_ORDER[perm, t]] += step[t]
+    cube = c4 // 8                                  # parent cube (coarse units: c / 2)
+    frac = c4 - 8 * cube                            # 8 x fractional part, distinct per axis
+    order = np.argsort(-frac, axis=1, kind="stable")
+    key = order[:, 0] * 3 + order[:, 1]
+    table = np.full(9, -1)
+    for n, (a, b, _) in enumerate(_KUHN_ORDER):
+        table[a * 3 + b] = n
+    return cube, table[key]
+
+
+def sphere_shell_kuhn(n_az, n_pol, n_rad, r_in=0.5, r_out=6.0, q=1.2, nref=2,
+                      wall_tag=SLIP, far_tag=FARFIELD):
+    """Spherical shell r in [r_in, r_out] around a unit-diameter sphere, as
+    the Kuhn triangulation of an (azimuth x polar x radial) index grid refined
+    2^nref times: the finest level is the Kuhn triangulation of the
+    (2^nref n_az) x (2^nref n_pol) x (2^nref n_rad) grid mapped by
+    phi = 2 pi i / N_az, theta = pi j / N_pol and the geometric radial map
+    r(s) = r_in + dr0 (q^s - 1) / (q - 1) (s in coarse index units,
+    dr0 = (r_out - r_in)(q - 1) / (q^n_rad - 1)).  The nodes of each polar
+    grid line collapse into one per radius; the tetrahedra with repeated
+    nodes there (three of the six in every cube of a polar row) are dropped.
+    The parent of a tetrahedron is the Kuhn tetrahedron of the grid of half
+    the resolution that contains it (Freudenthal refinement nests them), so
+    each coarse cell is the agglomerate of its surviving fine descendants.
+    Cells are numbered parent-major on every level."""
+    f = 2 ** nref
+    NA, NP, NR = n_az * f, n_pol * f, n_rad * f
+    dr0 = (r_out - r_in) * (q - 1.0) / (q ** n_rad - 1.0)
+    # nodes: (i mod NA, j, k) with the two polar lines merged per radius
+    ii, jj, kk = np.meshgrid(np.arange(NA), np.arange(NP + 1), np.arange(NR + 1), indexing="ij")
+    pole = (jj == 0) | (jj == NP)
+    keep = ~pole | (ii == 0)
+    nid = -np.ones((NA, NP + 1, NR + 1), dtype=np.int64)
+    nid[keep] = np.arange(int(keep.sum()))
+    nid[:, 0, :] = nid[0, 0, :]
+    nid[:, NP, :] = nid[0, NP, :]
+    s = kk[keep] / float(f)
+    r = r_in + dr0 * (q ** s - 1.0) / (q - 1.0)
+    r[kk[keep] == NR] = r_out
+    th = np.pi * jj[keep] / NP
+    ph = 2.0 * np.pi * ii[keep] / NA
+    xyz = np.stack([r * np.sin(th) * np.cos(ph), r * np.sin(th) * np.sin(ph), r * np.cos(th)], axis=1)
+    # finest Kuhn tetrahedra
+    org, perm = _kuhn_tets(NA, NP, NR)
+    verts = np.empty((len(org), 4, 3), dtype=np.int64)
+    verts[:, 0] = org
+    for t in range(3):
+        verts[:, t + 1] = verts[:, t]
+        verts[np.arange(len(org)), t + 1, _KUHN_ORDER[perm, t]] += 1
+    ids = nid[verts[..., 0] % NA, verts[..., 1], verts[..., 2]]
+    srt = np.sort(ids, axis=1)
+    good = np.all(srt[:, 1:] != srt[:, :-1], axis=1)
+    org, perm, ids = org[good], perm[good], ids[good]
+    # hierarchy: parent Kuhn tetrahedra level by level, as flat ids
+    lev_org, lev_perm = [org], [perm]
+    dims = [(NA, NP, NR)]
+    for l in range(nref):
+        o, p_ = _kuhn_parent(lev_org[-1], lev_perm[-1])
+        lev_org.append(o)
+        lev_perm.append(p_)
+        na, npl, nr = dims[-1]
+        dims.append((na // 2, npl // 2, nr // 2))
+
+    def flat(o, p_, d):
+        return ((o[:, 0] * d[1] + o[:, 1]) * d[2] + o[:, 2]) * 6 + p_
+
+    keys = [flat(lev_org[l], lev_perm[l], dims[l]) for l in range(nref + 1)]
+    # parent-major numbering from the coarsest level down
+    order = np.lexsort(tuple(keys[l] for l in range(nref + 1)))   # last key is primary
+    ids = ids[order]
+    keys = [k_[order] for k_ in keys]
+    def by_first_appearance(k_):
+        _, first, inv = np.unique(k_, return_index=True, return_inverse=True)
+        return np.argsort(np.argsort(first))[inv]
+
+    lid = [by_first_appearance(k_) for k_ in keys]      # per fine row: its cell's index on level l
+    parents = []
+    for l in range(nref):
+        par = np.empty(lid[l].max() + 1, dtype=np.int64)
+        par[lid[l]] = lid[l + 1]
+        parents.append(par.astype(np.int32))
+    tets = _orient_tets(xyz, ids.copy())
+    bf = _boundary_faces(tets)
+    rad = np.linalg.norm(xyz[bf], axis=2)
+    on_in = np.all(np.isclose(rad, r_in), axis=1)
+    on_out = np.all(np.isclose(rad, r_out), axis=1)
+    if not np.all(on_in | on_out):
+        raise ValueError("boundary face off the bounding spheres")
+    btags = np.where(on_in, wall_tag, far_tag).astype(np.int32)
+    return Mesh(3, np.ascontiguousarray(xyz), np.ascontiguousarray(tets, dtype=np.int32),
+                np.ascontiguousarray(bf, dtype=np.int32), btags, parents,
+                dict(kind="sphere_shell_kuhn", n_az=n_az, n_pol=n_pol, n_rad=n_rad, r_in=r_in, r_out=r_out,
+                     q=q, nref=nref))
+
+
 # Named workloads ----------------------------------------------------------
 
 def cylinder_euler_small(seed=0):
