@@ -174,6 +174,60 @@ def time_to_1e10(cgks, max_cycles, explicit_cap):
     return out
 
 
+# ---------------------------------------------------------------- ablations --
+
+ABLATIONS = (
+    ("DF relaxation (default)", {}),
+    ("no relaxation (fully implicit)", dict(df_relax=0)),
+    ("fixed weight 0.3", dict(df_relax=2, relax_beta=0.3)),
+    ("fixed weight 0.6", dict(df_relax=2, relax_beta=0.6)),
+    ("fixed weight 0.9", dict(df_relax=2, relax_beta=0.9)),
+    ("fixed-factor relaxation 0.5", dict(df_relax=3, relax_beta=0.5)),
+    ("fixed-factor relaxation 0.8", dict(df_relax=3, relax_beta=0.8)),
+    ("implicit CFL 2", dict(cfl_imp=2.0)),
+    ("implicit CFL 5", dict(cfl_imp=5.0)),
+    ("implicit CFL 20", dict(cfl_imp=20.0)),
+    ("implicit CFL 50", dict(cfl_imp=50.0)),
+    ("1 LU-SGS iteration", dict(n_sweeps=1)),
+    ("2 LU-SGS iterations", dict(n_sweeps=2)),
+    ("4 LU-SGS iterations", dict(n_sweeps=4)),
+    ("8 LU-SGS iterations", dict(n_sweeps=8)),
+    ("plain prolongation", dict(df_prolong=0)),
+)
+
+
+def ablations(cgks, max_cycles, hyper_cycles):
+    """The smoother and relaxation ablations: the steady Re 40 cylinder to 1e-10
+    from the free stream (FP64, autotuned) per variant, and a Mach 2, Re 300
+    cylinder (an unsteady wake: status and norms after a fixed number of
+    cycles from the ramped start) for the relaxation and prolongation ones."""
+    import numpy as np
+    import synthmesh as sm
+    mesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=2, wall_tag=sm.ISOTHERMAL)
+    prm = dict(mach=0.15, reynolds=40.0)
+    steady = {}
+    for name, form in ABLATIONS:
+        r, _ = time_to_tol(cgks, mesh, prm, 1e-10, max_cycles, **form)
+        steady[name] = {k: r[k] for k in ("converged", "cycles", "seconds", "final_norm", "min_norm")}
+        print(f"bench: ablation {name}: {r['cycles']} cycles", file=sys.stderr, flush=True)
+    hyper = {}
+    hp = dict(mach=2.0, reynolds=300.0)
+    for name, form in ABLATIONS[:7] + ABLATIONS[-1:]:
+        s = cgks.Solver(mesh, n_levels=3, **hp, **form)
+        initial_state(s, mesh, hp)
+        try:
+            h = s.run_cycles(hyper_cycles)
+            status = "ran"
+        except cgks.CgksError as e:
+            h, status = np.array([np.nan]), f"error {e.code}"
+        fin = h[np.isfinite(h)]
+        hyper[name] = {"status": status, "final_norm": float(fin[-1]) if len(fin) else None,
+                       "min_norm": float(fin.min()) if len(fin) else None}
+    return {"steady_re40": {"workload": "cylinder_ns_mach015_re40_8k", "tol": 1e-10, "variants": steady},
+            "mach2_re300": {"workload": "cylinder_ns_mach2_re300_8k (ramped start)", "cycles": hyper_cycles,
+                            "variants": hyper}}
+
+
 # --------------------------------------------------------------- CPU oracle --
 
 def cpu_model():
@@ -247,6 +301,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--explicit-cap", type=int, default=100000,
                     help="most steps of the explicit-solver comparison (0 skips it)")
+    ap.add_argument("--ablations", action="store_true",
+                    help="print the smoother/relaxation ablation table (one JSON line) instead")
+    ap.add_argument("--hyper-cycles", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -259,6 +316,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.ablations:
+        print(json.dumps({"ablations": ablations(cgks, args.max_cycles, args.hyper_cycles)}), flush=True)
+        return
     print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
     mesh, params = workload(args.workload)
     stream = torch.cuda.current_stream()

@@ -87,8 +87,11 @@ typedef struct cgks_params {
     int n_post;                /* post-smoothing steps: only 0 is supported (Sec. 5.2) */
     int n_sweeps;              /* LU-SGS iterations per coarse level, default 6 (Sec. 6.1) */
     int df_relax;              /* 1: DF relaxation of LU-SGS (Sec. 4.3); 0: fully implicit; 2: one fixed
-                                  relaxation weight relax_beta for every cell (the uniform relaxation
-                                  the DF weighting replaces) */
+                                  weight relax_beta in place of every cell's DF value; 3: the fixed-factor
+                                  relaxation of the remark in Sec. 4.3: relax_beta scales the implicit
+                                  time term V/dt_i, the flux Jacobian keeps full weight, and
+                                  (1 - relax_beta) (V/dt_i) times the cell's previous LU-SGS increment
+                                  (zero after restriction) joins the right-hand side */
     int df_prolong;            /* 1: DF-limited prolongation (Eq. prolongation); 0: plain */
     int precision;             /* CGKS_FP64 or CGKS_MIXED */
     double tau_c1;             /* Euler collision time: tau = c1 dt + c2 |dp|/(pl+pr) dt */
@@ -111,8 +114,8 @@ typedef struct cgks_params {
                                   last set (cgks_init_freestream, cgks_set_state) cfl_imp * min(1, k/N),
                                   for impulsive hypersonic starts; cycles discarded after a failure
                                   still count.  Default 0: cfl_imp throughout */
-    double relax_beta;         /* relaxation weight in [0, 1] used when df_relax = 2 (1 = fully implicit,
-                                  0 = explicit steps); default 0.5 */
+    double relax_beta;         /* relaxation weight in [0, 1] used when df_relax = 2 or 3 (1 = fully
+                                  implicit; with 2, 0 = explicit steps); default 0.5 */
     int shared_residual;       /* 1: one fine residual evaluation per V-cycle (not in the paper): the
                                   last fine pre-smoothing step's residual and input state are restricted
                                   instead of a new residual at the smoothed state, and the coarse

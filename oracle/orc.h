@@ -49,7 +49,7 @@ typedef struct orc_params {
     double slope_relax;
     double update_limit;
     int cfl_ramp;              /* implicit-CFL start-up ramp length in V-cycles; 0 = none */
-    double relax_beta;         /* fixed relaxation weight used when df_relax = 2 */
+    double relax_beta;         /* fixed relaxation weight used when df_relax = 2 or 3 */
     int shared_residual;       /* 1: restrict the last fine step's input state and residual */
 } orc_params;
 
@@ -100,6 +100,9 @@ int orc_prolong(orc_ctx* c, int level);
 int orc_vcycle(orc_ctx* c, double* norm_out);
 int orc_solve(orc_ctx* c, double tol, int max_cycles, int* cycles_out, double* history, int history_cap);
 int orc_stats(orc_ctx* c, int64_t* guard_hits, int64_t* prolong_skips);
+/* S * F of every fine face ([n_faces][nvar], oracle face order) from the last
+ * fine residual; ORC_EINVAL before any. */
+int orc_face_fluxes(orc_ctx* c, double* F);
 /* OpenMP threads of the loops over faces, cells and same-colour cells (every
  * result is bitwise the same for any count). */
 int orc_set_threads(int n);

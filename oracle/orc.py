@@ -248,6 +248,20 @@ class Oracle:
         rc = self._chk(lib().orc_solve(self.ctx, C.c_double(tol), max_cycles, C.byref(ncyc), _dp(hist), max_cycles))
         return rc, hist[:ncyc.value]
 
+    def flux_scale(self):
+        """max over cells and components of sum_f |S_f F_f| (the faces of the
+        cell) from the last fine residual: the scale the residual cancels from."""
+        nf = self.sizes[0][1]
+        F = np.zeros((nf, self.nvar))
+        self._chk(lib().orc_face_fluxes(self.ctx, _dp(F)))
+        LR = np.zeros((nf, 2), dtype=np.int32)
+        self._chk(lib().orc_face_geometry(self.ctx, 0, _ip(LR), None, None, None, None))
+        acc = np.zeros((self.sizes[0][0], self.nvar))
+        np.add.at(acc, LR[:, 0], np.abs(F))
+        inner = LR[:, 1] >= 0
+        np.add.at(acc, LR[inner, 1], np.abs(F[inner]))
+        return float(acc.max())
+
     def stats(self):
         a, b = C.c_int64(), C.c_int64()
         lib().orc_stats(self.ctx, C.byref(a), C.byref(b))

@@ -66,6 +66,7 @@ struct ReconOp {
 struct orc_ctx {
     orc_params p;
     int dim = 2, nvar = 4;
+    std::vector<double> face_flux;   /* S * F of every fine face from the last fine residual [nf][nvar] */
     std::vector<double> coords;
     std::vector<orc::Level> lv;
     std::vector<orc::ReconOp> rop;

@@ -577,7 +577,7 @@ int setup_mesh(orc_ctx* c, const orc_mesh* m, int n_levels, const int32_t* const
         L.W0 = L.W;
         L.F = L.W;
         L.Rstar = L.W;
-        L.dW = L.W;
+        L.dW.assign(L.W.size(), 0.0);
         L.rhs_last = L.W;
         L.alpha.assign(L.n, 1.0);
         if (l == 0) L.grad.assign((size_t)L.n * nv * dim, 0.0);

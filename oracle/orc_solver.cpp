@@ -286,6 +286,7 @@ void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew
         }
         for (int q = 0; q < nv; ++q) Ff[fi * nv + q] *= f.S;
     }
+    c->face_flux = Ff;
     R.assign((size_t)L0.n * nv, 0.0);
     gnew.assign((size_t)L0.n * nv * dim, 0.0);
     anew.assign(L0.n, 1.0);
@@ -387,6 +388,18 @@ void lusgs_iter(orc_ctx* c, int l, bool sequential) {
     for (int i = 0; i < L.n; ++i) {
         double sr = 0.0;
         for (int fi : L.cf[i]) sr += L.faces[fi].S * rf[fi];
+        if (p.df_relax == 3) {
+            /* The fixed-factor relaxation the paper contrasts with DF relaxation
+             * (remark in Sec. 4.3): beta scales the implicit time term only, the
+             * flux Jacobian keeps full weight, and (1 - beta) times the cell's
+             * previous increment joins the right-hand side (with V/dt_i: the
+             * printed term lacks it and is dimensionally a state, not a flux). */
+            al[i] = 1.0;
+            D[i] = p.relax_beta * L.V[i] / dti[i] + 0.5 * sr;
+            for (int q = 0; q < nv; ++q)
+                rhs[i * nv + q] += (1.0 - p.relax_beta) * (L.V[i] / dti[i]) * L.dW[i * nv + q];
+            continue;
+        }
         /* relaxation weight: DF (Sec. 4.3), one fixed weight, or fully implicit */
         al[i] = p.df_relax == 1 ? L.alpha[i] : (p.df_relax == 2 ? p.relax_beta : 1.0);
         D[i] = al[i] * (L.V[i] / dti[i] + 0.5 * sr) + (1.0 - al[i]) * L.V[i] / dte[i];
@@ -537,6 +550,7 @@ void restrict_level(orc_ctx* c, int l, const std::vector<double>& res_fine,
             G.W0[I * nv + q] = w[q] / G.V[I];
             G.W[I * nv + q] = G.W0[I * nv + q];
             G.Rstar[I * nv + q] = r[q];
+            G.dW[I * nv + q] = 0.0;   /* no previous LU-SGS increment in this cycle */
         }
         G.alpha[I] = amin;
     }
@@ -749,6 +763,16 @@ int orc_residual(orc_ctx* c, int level, double* R, double* gradW_new, double* al
     if (R)
         for (size_t k = 0; k < Res.size(); ++k) R[k] = -(Res[k] + L.F[k]);
     if (alpha_out) std::copy(L.alpha.begin(), L.alpha.end(), alpha_out);
+    return ORC_OK;
+}
+
+/* S * F of every fine face (oracle face order, [nf][nvar]) from the last fine
+ * residual evaluation: the scale of the residual's cancellation. */
+int orc_face_fluxes(orc_ctx* c, double* F) {
+    int rc = check(c, 0);
+    if (rc) return rc;
+    if (c->face_flux.empty()) return ORC_EINVAL;
+    std::copy(c->face_flux.begin(), c->face_flux.end(), F);
     return ORC_OK;
 }
 

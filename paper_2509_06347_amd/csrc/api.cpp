@@ -153,7 +153,7 @@ void enqueue_restrict(cgks_ctx* c, int l) {
     if (l == 0)
         launch_fine_residual(c, FINE_RESTRICT);
     else
-        launch_coarse_rhs(c, l, COARSE_RHS);
+        launch_coarse_rhs(c, l, COARSE_EVAL);
     launch_restrict(c, l);
     launch_coarse_rhs(c, l + 1, COARSE_FORCING);
 }
@@ -279,8 +279,11 @@ int upload(cgks_ctx* c) {
             }
         }
     if ((int)fperm.size() != nf) return fail(c, CGKS_EMESH, "face without an owner cell");
+    std::vector<double> fX((size_t)nf * ng * dim);
     for (int e = 0; e < nf; ++e) {
         const HFace& F = H.faces[fperm[e]];
+        for (int g = 0; g < ng; ++g)
+            for (int d = 0; d < dim; ++d) fX[((size_t)e * ng + g) * dim + d] = F.gp[g][d];
         fL[e] = F.L;
         fR[e] = F.R;
         fS[e] = F.S;
@@ -329,11 +332,9 @@ int upload(cgks_ctx* c) {
     TRY(dalloc(c, &f.Wsave, (size_t)nv * n));
     TRY(dalloc(c, &f.gsave, (size_t)nv * dim * n));
     TRY(dalloc(c, &f.asave, n));
-    TRY(dalloc(c, &f.gps, (size_t)ng * nv * (1 + dim) * n * ns));
-    TRY(dalloc(c, &f.gho, (size_t)ng * nv * (1 + dim) * nf));
-    TRY(dalloc(c, &f.fF, (size_t)nv * ng * nf));
-    TRY(dalloc(c, &f.fG, (size_t)nv * ng * nf));
-    TRY(dalloc(c, &f.fa, (size_t)ng * nf));
+    TRY(dalloc(c, &f.poly, (size_t)(dim == 2 ? 40 : 80) * n));
+    TRY(dalloc(c, &f.fX, (size_t)nf * ng * dim)); TRY(h2d(c, f.fX, fX));
+    TRY(dalloc(c, &f.fout, (size_t)nf * (2 * nv + 1)));
     TRY(dalloc(c, &f.R, (size_t)nv * n));
     TRY(dalloc(c, &f.gnew, (size_t)nv * dim * n));
     TRY(dalloc(c, &f.anew, n));
@@ -491,7 +492,7 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (!(p->slope_relax > 0.0 && p->slope_relax <= 1.0)) return CGKS_EINVAL;
     if (!(p->update_limit <= 1.0)) return CGKS_EINVAL;
     if (p->cfl_ramp < 0) return CGKS_EINVAL;
-    if (p->df_relax < 0 || p->df_relax > 2) return CGKS_EINVAL;
+    if (p->df_relax < 0 || p->df_relax > 3) return CGKS_EINVAL;
     if (!(p->relax_beta >= 0.0 && p->relax_beta <= 1.0)) return CGKS_EINVAL;
     if (p->shared_residual != 0 && p->shared_residual != 1) return CGKS_EINVAL;
     int ndev = 0;
@@ -679,7 +680,7 @@ int cgks_residual(cgks_ctx* c, int level, double* R, double* gradW_new, double* 
         return CGKS_OK;
     }
     CoarseDev& D = c->coarse[level - 1];
-    launch_coarse_rhs(c, level, COARSE_RHS);
+    launch_coarse_rhs(c, level, COARSE_EVAL);
     HIPCHK(hipGetLastError());
     if (R) {
         std::vector<double> h;
@@ -707,7 +708,7 @@ int cgks_time_steps(cgks_ctx* c, int level, double* dt_exp, double* dt_imp) {
         de = c->fine.dt;
         di = c->fine.dti;
     } else {
-        launch_coarse_rhs(c, level, COARSE_RHS);
+        launch_coarse_rhs(c, level, COARSE_EVAL);
         de = c->coarse[level - 1].dte;
         di = c->coarse[level - 1].dti;
     }

@@ -65,9 +65,9 @@ struct FineDev {
     double *fn, *fS;                  /* fn [dim][nf] */
     double *W, *grad, *alpha;         /* state */
     double *Wsave, *gsave, *asave;    /* start-of-cycle copy for roll-back */
-    double *gps;                      /* [ngp][nv + nv*dim][n][nslot] Gauss-point states of each cell's side */
-    double *gho;                      /* [ngp][nv + nv*dim][nf] ghost states of boundary faces */
-    double *fF, *fG, *fa;             /* [nv][ngp*nf], [nv][ngp*nf], [ngp*nf] */
+    double *poly;                     /* [n][40 | 80] per-cell polynomial record (reconstruction -> flux) */
+    double *fX;                       /* [nf][ngp][dim] Gauss points of each face */
+    double *fout;                     /* [nf][2 nv + 1] per face: sum wS F, sum wS W(dt), DF product */
     double *R, *gnew, *anew, *dt, *dti;
     double *res;                      /* -R of the restriction evaluation */
     double *Wpre;                     /* input state of a fine step whose residual is restricted */
@@ -176,7 +176,10 @@ enum { FINE_EVAL = 0, FINE_STEP = 1, FINE_STEP_NORM = 2, FINE_RESTRICT = 3 };
 /* flag on a step mode: also keep -R in res and the step's input state in Wpre */
 enum { FINE_KEEP = 8 };
 /* modes of launch_coarse_rhs */
-enum { COARSE_RHS = 0, COARSE_FORCING = 1 };
+/* Coarse right-hand-side kernel modes: inside an LU-SGS iteration (fused
+ * first-colour forward step, fixed-factor term), the FAS forcing, and a plain
+ * evaluation of Res + F with no side effect on the increments. */
+enum { COARSE_RHS = 0, COARSE_FORCING = 1, COARSE_EVAL = 2 };
 }  // namespace cgks
 
 #endif

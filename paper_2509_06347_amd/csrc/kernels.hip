@@ -58,10 +58,35 @@ __device__ __forceinline__ double implicit_cfl(const KParams& kp) {
     return kp.cfl_imp * fmin(1.0, (double)(k > 1 ? k : 1) / (double)kp.cfl_ramp);
 }
 
-/* Relaxation weight of a coarse cell's LU-SGS (Sec. 4.3): its DF value, one
- * fixed weight for every cell, or 1 (fully implicit). */
+/* Weight of the flux-Jacobian terms of a coarse cell's LU-SGS (Sec. 4.3): its
+ * DF value, one fixed weight for every cell, or 1 (fully implicit, and the
+ * fixed-factor relaxation of df_relax = 3, which scales the time term only). */
 __device__ __forceinline__ double relax_weight(const KParams& kp, double alpha) {
     return kp.df_relax == 1 ? alpha : (kp.df_relax == 2 ? kp.relax_beta : 1.0);
+}
+
+/* Diagonal of a coarse cell's LU-SGS.  DF relaxation and its variants blend
+ * the implicit and the explicit diagonals with the weight above (Eq.
+ * DF-relaxation-hybrid); the fixed-factor relaxation the paper contrasts it
+ * with (remark in Sec. 4.3) scales the implicit time term by beta alone. */
+__device__ __forceinline__ double lusgs_diagonal(const KParams& kp, double alpha, double V, double dti, double dte,
+                                                 double sr) {
+    if (kp.df_relax == 3) return kp.relax_beta * V / dti + 0.5 * sr;
+    const double a = relax_weight(kp, alpha);
+    return a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+}
+
+/* Right-hand side of the fixed-factor relaxation: (1 - beta) times the cell's
+ * increment of the previous LU-SGS iteration (zero after restriction), scaled
+ * by V / dt_i so that it is a flux like the residual (the printed term lacks
+ * the scale). */
+template <int NV, class T>
+__device__ __forceinline__ void fixed_factor_rhs(const KParams& kp, const CoarseDev& c, int I, double V, double dti,
+                                                 double* rhs) {
+    if (kp.df_relax != 3) return;
+    const T* dW = reinterpret_cast<const T*>(c.dW);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) rhs[q] += (1.0 - kp.relax_beta) * (V / dti) * (double)dW[q * c.n + I];
 }
 
 template <int D>
@@ -72,6 +97,15 @@ struct Shape {
     static constexpr int NG = (D == 2) ? 2 : 3;     /* Gauss points per face */
     static constexpr int NC = NV * (1 + D);         /* state + gradient per Gauss point */
     static constexpr int NCOL = NS * (1 + D);       /* operator inputs */
+    static constexpr int NK = NQ + D;               /* coefficients per component: p^2 part, Green-Gauss part */
+    /* per-cell polynomial record handed from the reconstruction to the flux:
+     * coefficients [NV][NK], cell averages [NV], basis means [NQ], centroid [D], 1/h */
+    static constexpr int REC_W = NV * NK;
+    static constexpr int REC_MEAN = REC_W + NV;
+    static constexpr int REC_C = REC_MEAN + NQ;
+    static constexpr int REC_IH = REC_C + D;
+    static constexpr int NPR = (D == 2) ? 40 : 80;  /* record stride (3-D padded to 16-byte rows) */
+    static constexpr int FO = 2 * NV + 1;           /* per-face output: sum wS F, sum wS W(dt), DF product */
 };
 
 /* Exponents of the scaled monomials, same order as the host operator. */
@@ -137,12 +171,13 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
  * faces x Gauss points).  Phase 1, one thread per (cell, component): the p^2
  * coefficients from the operator, the alpha-scaled Green-Gauss gradient and
  * the nonlinear weights, into LDS; the component-0 thread also forms the local
- * time steps.  Phase 2, one thread per (cell, face slot, Gauss point): value
- * and gradient of every component at its point; the cell's positivity guard
- * is an LDS flag over its points; states are written [k][component][cell][slot]
- * and boundary slots add their ghost state.  Phase 1 also leaves the cell's
- * state and basis means in LDS for phase 2.  Per cell and component the
- * arithmetic is that of a one-thread-per-cell evaluation. */
+ * time steps.  Phase 2, one thread per (cell, face slot, Gauss point): the
+ * combined polynomial's value at its point, for the cell's positivity guard
+ * (an LDS flag over its points).  Then the block writes each cell's polynomial
+ * record (coefficients, zeroed when the guard holds so that the cell is
+ * constant; cell averages; basis means; centroid; 1/h), contiguous per cell,
+ * which the flux kernel evaluates at its Gauss points.  Per cell and component
+ * the arithmetic is that of a one-thread-per-cell evaluation. */
 constexpr int RMAXC = 64;   /* most cells per reconstruction block */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
 template <int D>
@@ -303,96 +338,128 @@ __global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int
         if (!(P.rho > 0.0 && P.p > 0.0)) atomicOr(&bad[cl], 1);
     }
     __syncthreads();
-    if (!live) return;
-    const bool guard = bad[cl] != 0;
-    if (guard && j == 0) atomicAdd(f.guard, 1ull);
-    /* gradients from the basis derivatives at the point (recomputed: fewer live
-     * registers across the barrier); the guarded cell is constant */
-    double phi[NQ], dphi[NQ][3], gx[NV][D];
-    basis_at<D>(X, phi, dphi);
-    const double ih = 1.0 / f.h[i];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (guard) Wx[q] = wsh[q][cl];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double gd = coef[q * NK + NQ + d][cl];
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) gd += coef[q * NK + m][cl] * dphi[m][d];
-            gx[q][d] = guard ? 0.0 : gd * ih;
-        }
-    }
-    double* out = f.gps + ((size_t)(k * NC) * n + i) * NS + s;
-    const size_t cs = (size_t)n * NS;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) out[q * cs] = Wx[q];
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-#pragma unroll
-        for (int d = 0; d < D; ++d) out[(NV + q * D + d) * cs] = gx[q][d];
-    if (f.slot_nbr[s * n + i] < 0) {
-        const KParams kp = localize(kp0, f.ptab, f.pid, i);
-        double nout[D], Wg[NV], gg[NV][D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) nout[d] = f.slot_n[(d * NS + s) * n + i];
-        ghost_state<D, true>(kp, f.slot_tag[s * n + i], Wx, gx, nout, Wg, gg);
-        const int fid = f.slot_face[s * n + i] >> 1;
-        double* og = f.gho + (size_t)(k * NC) * nf + fid;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) og[(size_t)q * nf] = Wg[q];
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-#pragma unroll
-            for (int d = 0; d < D; ++d) og[(size_t)(NV + q * D + d) * nf] = gg[q][d];
+    if (live && j == 0 && bad[cl]) atomicAdd(f.guard, 1ull);
+    /* the cells' polynomial records, written contiguously by the whole block */
+    constexpr int NPR = S::NPR;
+    const int ncell = min(cells, n - i0);
+    for (int e = t; e < ncell * NPR; e += blockDim.x) {
+        const int c2 = e / NPR, jj = e - c2 * NPR, ii = i0 + c2;
+        double v = 0.0;
+        if (jj < S::REC_W) v = bad[c2] ? 0.0 : coef[jj][c2];
+        else if (jj < S::REC_MEAN) v = wsh[jj - S::REC_W][c2];
+        else if (jj < S::REC_C) v = msh[jj - S::REC_MEAN][c2];
+        else if (jj < S::REC_IH) v = f.C[(size_t)(jj - S::REC_C) * n + ii];
+        else if (jj == S::REC_IH) v = 1.0 / f.h[ii];
+        f.poly[(size_t)ii * NPR + jj] = v;
     }
 }
 
+/* Value and gradient of every component of a cell's combined polynomial at
+ * the point x (absolute coordinates), from its record. */
 template <int D>
-__global__ void __launch_bounds__(BLOCK) k_flux(FineDev f, KParams kp0) {
+__device__ __forceinline__ void eval_poly(const double* __restrict__ rec, const double* x, double* W,
+                                          double (*g)[D]) {
     using S = Shape<D>;
-    constexpr int NV = S::NV, NG = S::NG, NC = S::NC;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nf = f.nf;
-    if (t >= NG * nf) return;
-    const int k = t / nf, fc = t - k * nf;
-    const KParams kp = localize(kp0, f.ptab, f.fpid, fc);
-    double WL[NV], WR[NV], gL[NV][D], gR[NV][D], nn[D];
-    constexpr int NS = S::NS;
-    const int L = f.fL[fc], R = f.fR[fc], sl = f.fslot[fc];
-    const size_t cs = (size_t)f.n * NS;
-    const double* sL = f.gps + ((size_t)(k * NC) * f.n + L) * NS + (sl & 7);
-    const double* sR;
-    size_t rs;
-    if (R >= 0) {
-        sR = f.gps + ((size_t)(k * NC) * f.n + R) * NS + (sl >> 3);
-        rs = cs;
-    } else {
-        sR = f.gho + (size_t)(k * NC) * nf + fc;
-        rs = nf;
-    }
+    constexpr int NV = S::NV, NQ = S::NQ, NK = S::NK;
+    const double ih = rec[S::REC_IH];
+    double X[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) X[d] = (x[d] - rec[S::REC_C + d]) * ih;
+    double phi[NQ], dphi[NQ][3], pm[NQ];
+    basis_at<D>(X, phi, dphi);
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) pm[m] = phi[m] - rec[S::REC_MEAN + m];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        WL[q] = sL[q * cs];
-        WR[q] = sR[q * rs];
+        const double* c = rec + q * NK;
+        double v = rec[S::REC_W + q];
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) v += c[m] * pm[m];
+#pragma unroll
+        for (int d = 0; d < D; ++d) v += c[NQ + d] * X[d];
+        W[q] = v;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            gL[q][d] = sL[(NV + q * D + d) * cs];
-            gR[q][d] = sR[(NV + q * D + d) * rs];
+            double gd = c[NQ + d];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) gd += c[m] * dphi[m][d];
+            g[q][d] = gd * ih;
         }
     }
+}
+
+/* BGK flux (Sec. 2), one lane per (face, Gauss point): the face's Gauss
+ * points sit in adjacent lanes of one wave (64 / NG faces per wave; in 3-D
+ * the last lane idles), so the two cells' records they read are shared.  The
+ * face's first lane sums the lanes' S/NG-weighted fluxes and states at
+ * t = dt in Gauss-point order and multiplies their DF factors, and writes
+ * the face's record [sum wS F, sum wS W(dt), DF product]. */
+constexpr int FTHREADS = 256;
+template <int D>
+__global__ void __launch_bounds__(FTHREADS) k_flux(FineDev f, KParams kp0) {
+    using S = Shape<D>;
+    constexpr int NV = S::NV, NG = S::NG, NPR = S::NPR, FO = S::FO, NS = S::NS;
+    constexpr int FPW = 64 / NG;
+    const int lane = threadIdx.x & 63;
+    const long wv = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int k = lane % NG, lf = lane / NG;
+    const long fcl = wv * FPW + lf;
+    const int nf = f.nf;
+    const bool live = lf < FPW && fcl < nf;
+    const int fc = live ? (int)fcl : 0;
+    double F[NV], G[NV], a = 1.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) nn[d] = f.fn[d * nf + fc];
-    double dt = f.dt[L];
-    if (R >= 0) dt = fmin(dt, f.dt[R]);
-    double F[NV], G[NV], a;
-    gks_flux<D>(kp, WL, gL, WR, gR, nn, dt, F, G, &a);
-    const double ws = f.fS[fc] / NG;
+    for (int q = 0; q < NV; ++q) F[q] = G[q] = 0.0;
+    if (live) {
+        const KParams kp = localize(kp0, f.ptab, f.fpid, fc);
+        const int L = f.fL[fc], R = f.fR[fc];
+        double x[D], nn[D], WL[NV], WR[NV], gL[NV][D], gR[NV][D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            x[d] = f.fX[((size_t)fc * NG + k) * D + d];
+            nn[d] = f.fn[(size_t)d * nf + fc];
+        }
+        eval_poly<D>(f.poly + (size_t)L * NPR, x, WL, gL);
+        if (R >= 0) {
+            eval_poly<D>(f.poly + (size_t)R * NPR, x, WR, gR);
+        } else {
+            const int tag = f.slot_tag[(size_t)(f.fslot[fc] & 7) * f.n + L];
+            ghost_state<D, true>(kp, tag, WL, gL, nn, WR, gR);
+        }
+        double dt = f.dt[L];
+        if (R >= 0) dt = fmin(dt, f.dt[R]);
+        double Fk[NV], Gk[NV];
+        gks_flux<D>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
+        const double ws = f.fS[fc] / NG;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            F[q] = ws * Fk[q];
+            G[q] = ws * Gk[q];
+        }
+    }
+    (void)NS;
+    const int base = lane - k;
+    double out[FO];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        f.fF[(size_t)q * NG * nf + t] = ws * F[q];
-        f.fG[(size_t)q * NG * nf + t] = ws * G[q];
+        double sf = 0.0, sg = 0.0;
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            sf += __shfl(F[q], base + j);
+            sg += __shfl(G[q], base + j);
+        }
+        out[q] = sf;
+        out[NV + q] = sg;
     }
-    f.fa[t] = a;
+    double ap = 1.0;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) ap *= __shfl(a, base + j);
+    out[2 * NV] = ap;
+    if (live && k == 0) {
+        double* o = f.fout + (size_t)fc * FO;
+#pragma unroll
+        for (int e = 0; e < FO; ++e) o[e] = out[e];
+    }
 }
 
 /* Block-level fixed-order sum of one double per thread. */
@@ -474,20 +541,14 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
             double nn[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) nn[d] = f.slot_n[(d * NS + s) * n + i];
+            const double* o = f.fout + (size_t)fc * S::FO;
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
-                double fs = 0.0, gs = 0.0;
+                R[q] += sg * o[q];
 #pragma unroll
-                for (int k = 0; k < NG; ++k) {
-                    fs += f.fF[(size_t)q * NG * nf + k * nf + fc];
-                    gs += f.fG[(size_t)q * NG * nf + k * nf + fc];
-                }
-                R[q] += sg * fs;
-#pragma unroll
-                for (int d = 0; d < D; ++d) Gs[q][d] += gs * nn[d];
+                for (int d = 0; d < D; ++d) Gs[q][d] += o[NV + q] * nn[d];
             }
-#pragma unroll
-            for (int k = 0; k < NG; ++k) a *= f.fa[k * nf + fc];
+            a *= o[2 * NV];
         }
         const double V = f.V[i];
         const double sc = a / V;
@@ -654,17 +715,20 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
     const double dte = kp.cfl_exp * V / lam, dti = implicit_cfl(kp) * V / lam;
     c.dte[I] = dte;
     c.dti[I] = dti;
+    double rhs[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = Res[q] + c.F[q * n + I];
-    const double a = relax_weight(kp, c.alpha[I]);
-    const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+    for (int q = 0; q < NV; ++q) rhs[q] = Res[q] + c.F[q * n + I];
+    if (mode == COARSE_RHS) fixed_factor_rhs<NV, T>(kp, c, I, V, dti, rhs);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = rhs[q];
+    const double Dd = lusgs_diagonal(kp, c.alpha[I], V, dti, dte, sr);
     c.D[I] = Dd;
     /* The forward sweep of the first colour has no lower neighbours: its
      * correction is rhs / D, formed here exactly as the sweep would. */
     if (I < hi1) {
         T* dW = reinterpret_cast<T*>(c.dW);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dW[q * n + I] = (T)(Res[q] + c.F[q * n + I]) / (T)Dd;
+        for (int q = 0; q < NV; ++q) dW[q * n + I] = (T)rhs[q] / (T)Dd;
     }
 }
 
@@ -764,12 +828,11 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
     c.dti[I] = dti;
     double rhs[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        rhs[q] = Res[q] + c.F[q * n + I];
-        c.rhs[q * n + I] = rhs[q];
-    }
-    const double a = relax_weight(kp, c.alpha[I]);
-    const double Dd = a * (V / dti + 0.5 * sr) + (1.0 - a) * V / dte;
+    for (int q = 0; q < NV; ++q) rhs[q] = Res[q] + c.F[q * n + I];
+    if (mode == COARSE_RHS) fixed_factor_rhs<NV, T>(kp, c, I, V, dti, rhs);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = rhs[q];
+    const double Dd = lusgs_diagonal(kp, c.alpha[I], V, dti, dte, sr);
     c.D[I] = Dd;
     if (I < hi1) {
         T* dW = reinterpret_cast<T*>(c.dW);
@@ -982,12 +1045,14 @@ __global__ void __launch_bounds__(CBLOCK) k_restrict(CoarseDev c, const double* 
     }
     const double iv = 1.0 / c.V[I];
     T* Rs = reinterpret_cast<T*>(c.Rstar);
+    T* dW = reinterpret_cast<T*>(c.dW);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         const double w0 = w[q] * iv;
         c.W0[q * n + I] = w0;
         c.W[q * n + I] = w0;
         Rs[q * n + I] = r[q];
+        dW[q * n + I] = 0;        /* no previous LU-SGS increment in this cycle */
     }
     c.alpha[I] = amin;
 }
@@ -1071,8 +1136,10 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
         const int cells = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
         k_recon2<D><<<blocks(f.n, cells), cells * S::NS * S::NG, 0, st>>>(f, c->kp, cells);
     } else if (which == 1) {
+        /* 64 / NG faces per wave */
         const int b = block ? block : c->blk_flux;
-        k_flux<D><<<blocks((long)f.nf * f.ngp, b), b, 0, st>>>(f, c->kp);
+        const long waves = ((long)f.nf + 64 / Shape<D>::NG - 1) / (64 / Shape<D>::NG);
+        k_flux<D><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
     } else {
         /* the norm partials use a fixed 256-thread block */
         const int m = mode & ~FINE_KEEP;

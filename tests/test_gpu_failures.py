@@ -77,7 +77,7 @@ def test_out_of_range_node_is_rejected(cg):
 
 @pytest.mark.parametrize("bad", [dict(slope_relax=0.0), dict(slope_relax=1.5), dict(update_limit=1.5),
                                  dict(precision=7), dict(mach=0.0), dict(n_post=1), dict(cfl_ramp=-1),
-                                 dict(df_relax=3), dict(df_relax=2, relax_beta=1.5)])
+                                 dict(df_relax=4), dict(df_relax=3, relax_beta=1.5)])
 def test_invalid_parameters_are_rejected(cg, bad):
     with pytest.raises(cg.CgksError) as e:
         cg.Solver(_mesh(), n_levels=3, **dict(dict(mach=0.5), **bad))

@@ -290,11 +290,13 @@ def test_shared_residual_parity(cg, orc, precision):
         assert np.abs(Wg - Wo).max() <= 1e-5 * np.abs(Wo).max()
 
 
-def test_fixed_relaxation_parity(cg, orc):
-    """One fixed relaxation weight for every coarse cell (df_relax = 2) instead
-    of the DF weights: the coarse chain and a 3-cycle trajectory."""
+@pytest.mark.parametrize("df_relax", [2, 3])
+def test_fixed_relaxation_parity(cg, orc, df_relax):
+    """One fixed relaxation weight for every coarse cell instead of the DF
+    weights (df_relax = 2), and the fixed-factor relaxation of the remark in
+    Sec. 4.3 (df_relax = 3): the coarse chain and a 3-cycle trajectory."""
     mesh, params = CASES["ragged_farfield"][0](), CASES["ragged_farfield"][1]
-    g, o = _pair(cg, orc, mesh, df_relax=2, relax_beta=0.6, **params)
+    g, o = _pair(cg, orc, mesh, df_relax=df_relax, relax_beta=0.6, **params)
     W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=13)
     _coarse_chain(g, o, W, grad, alpha)
     for s in (g, o):

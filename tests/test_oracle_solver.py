@@ -316,6 +316,43 @@ def test_fixed_relaxation_reduces_to_pinned_cases(orc, small_mesh):
     assert not np.array_equal(Wc, Wa)
 
 
+def test_fixed_factor_relaxation_reduces_to_pinned_cases(orc, small_mesh):
+    """df_relax = 3 (the fixed-factor relaxation of the remark in Sec. 4.3,
+    beta on the implicit time term and (1 - beta) V/dt_i times the previous
+    increment on the right-hand side): beta = 1 is the fully implicit LU-SGS bit
+    for bit; the first iteration after restriction (no previous increment) is
+    the fully implicit iteration at the implicit CFL divided by beta (bit for
+    bit for beta = 1/2, an exact scaling); the second iteration is not (the
+    previous increment enters)."""
+    def coarse(**kw):
+        o = _prepared(orc, small_mesh, mach=0.5, **kw)
+        o.smooth(0, 1)
+        o.restrict(0)
+        return o
+    a, b = coarse(df_relax=3, relax_beta=1.0), coarse(df_relax=0)
+    for o in (a, b):
+        o.smooth(1, 2)
+    assert np.array_equal(a.get_level_state(1)[0], b.get_level_state(1)[0])
+    c, d = coarse(df_relax=3, relax_beta=0.5), coarse(df_relax=0, cfl_imp=20.0)
+    for o in (c, d):
+        o.smooth(1, 1)
+    Wc, Wd = c.get_level_state(1)[0], d.get_level_state(1)[0]
+    assert np.array_equal(Wc, Wd)
+    for o in (c, d):
+        o.smooth(1, 1)
+    Wc2, Wd2 = c.get_level_state(1)[0], d.get_level_state(1)[0]
+    assert not np.array_equal(Wc2, Wd2)
+    # the previous increment is cleared by the next restriction
+    e = coarse(df_relax=3, relax_beta=0.5)
+    e.smooth(1, 3)
+    e.restrict(0)
+    f = coarse(df_relax=0, cfl_imp=20.0)
+    f.restrict(0)
+    for o in (e, f):
+        o.smooth(1, 1)
+    assert np.array_equal(e.get_level_state(1)[0], f.get_level_state(1)[0])
+
+
 def test_cfl_ramp_cycles_equal_fixed_cfl_cycles(orc, small_mesh):
     """The start-up ramp of N cycles runs the k-th V-cycle after a state is set at
     CFL cfl_imp * k / N: with N = 4 and cfl_imp = 10 the first two cycles are,
