@@ -328,11 +328,24 @@ int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, floa
 /* Fine-level initial state of a 2-D context from the network.  fmean/fstd
  * standardise the features, tmean/tstd de-standardise the targets (host
  * float[5] and float[4]).  Wall distance is taken to the nearest wall-face
- * centre.  Cells whose prediction is non-finite or non-physical take the free
- * stream; n_fallback (may be NULL) receives their count.  Gradients are
- * zeroed and alpha set to 1, as cgks_set_state does. */
+ * centre (the features of cgks_mlp_features).  Cells whose features leave the
+ * training range set with cgks_mlp_set_range, or whose prediction is
+ * non-finite or non-physical, take the free stream; n_fallback (may be NULL)
+ * receives their count.  Gradients are zeroed and alpha set to 1, as
+ * cgks_set_state does. */
 int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, const float* fstd, const float* tmean,
                        const float* tstd, int* n_fallback);
+/* The raw warm-start features of a 2-D context's fine cells, X [n][5] float in
+ * original cell order (host or device memory per `mem`): Mach, log10 Re (0
+ * for Euler), centroid x and y, and the distance to the nearest wall-face
+ * centre (0 without walls).  The same device kernel feeds cgks_init_from_mlp,
+ * so the training data and the warm start's inputs share one definition. */
+int cgks_mlp_features(cgks_ctx* c, float* X, int mem);
+/* Training range of the raw features (host float[5] each, lo <= hi): a warm
+ * start gives the free stream to every cell with a feature outside it (a
+ * problem whose Mach or Reynolds number lies outside falls back entirely).
+ * NULL, NULL clears the range (the default: no range check). */
+int cgks_mlp_set_range(cgks_mlp* m, const float* lo, const float* hi);
 
 /* Counters: positivity-guard hits of the reconstruction; prolongation
  * corrections applied only in part or not at all by the update safeguard. */

@@ -98,6 +98,8 @@ _sigs = {
     "cgks_mlp_grads": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
     "cgks_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
     "cgks_init_from_mlp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.POINTER(C.c_int)]),
+    "cgks_mlp_set_range": (C.c_int, [_P, _P, _P]),
+    "cgks_mlp_features": (C.c_int, [_P, _P, C.c_int]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -211,6 +213,13 @@ class Solver:
         V, Cc = np.zeros(n), np.zeros((n, self.dim))
         self._check(_lib.cgks_cell_geometry(self.ctx, level, V.ctypes.data_as(_D), Cc.ctypes.data_as(_D)))
         return V, Cc
+
+    def mlp_features(self):
+        """Raw warm-start features [n, 5] (float32) of the fine cells: Mach,
+        log10 Re, centroid x, y, distance to the nearest wall-face centre."""
+        X = np.zeros((self.sizes[0][0], 5), dtype=np.float32)
+        self._check(_lib.cgks_mlp_features(self.ctx, X.ctypes.data, HOST))
+        return X
 
     # state -------------------------------------------------------------------
     def init_freestream(self):
@@ -439,6 +448,15 @@ class MLP:
         loss = C.c_float()
         self._check(_lib.cgks_mlp_train_step(self.h, px, py, n, C.c_float(lr), C.byref(loss)), "cgks_mlp_train_step")
         return float(loss.value)
+
+    def set_range(self, lo, hi):
+        """Training range of the raw features; a warm start falls back to the
+        free stream in cells outside it (None, None clears it)."""
+        if lo is None:
+            self._check(_lib.cgks_mlp_set_range(self.h, None, None))
+            return
+        a, b = _f32(lo, 5), _f32(hi, 5)
+        self._check(_lib.cgks_mlp_set_range(self.h, a.ctypes.data, b.ctypes.data), "cgks_mlp_set_range")
 
     def init_solver(self, solver, fmean, fstd, tmean, tstd):
         """Warm-start a 2-D solver's fine state; returns the number of fallback cells."""

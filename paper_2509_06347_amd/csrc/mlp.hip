@@ -205,17 +205,53 @@ __global__ void k_to_bf16(const float* a, __bf16* b, int cnt) {
     if (t < cnt) b[t] = (__bf16)a[t];
 }
 
+/* Raw features of every fine cell [n][5]: Mach, log10 Re, centroid x and y
+ * (SoA centroids C [2][n]) and the distance to the nearest wall-face centre
+ * (wc [nw][2]; 0 without walls).  The one definition used both to build
+ * training data and to evaluate the network for a warm start. */
+__global__ void k_features(const double* C, int n, const double* wc, int nw, double mach, double lre, float* X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = C[i], y = C[n + i];
+    double d2 = nw > 0 ? 1e300 : 0.0;
+    for (int k = 0; k < nw; ++k) {
+        const double dx = x - wc[2 * k], dy = y - wc[2 * k + 1];
+        d2 = fmin(d2, dx * dx + dy * dy);
+    }
+    float* o = X + (size_t)i * 5;
+    o[0] = (float)mach;
+    o[1] = (float)lre;
+    o[2] = (float)x;
+    o[3] = (float)y;
+    o[4] = (float)sqrt(d2);
+}
+
+/* Standardised features (X - mean) / std in place; a cell whose features lie
+ * outside the training range [lo, hi] (when a range is set) is marked for the
+ * free-stream fallback. */
+__global__ void k_standardise(float* X, int n, const float* mean_std, const float* range, int* out_of_range) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool out = false;
+    for (int k = 0; k < 5; ++k) {
+        const float v = X[(size_t)i * 5 + k];
+        if (range && (v < range[k] || v > range[5 + k])) out = true;
+        X[(size_t)i * 5 + k] = (v - mean_std[k]) / mean_std[5 + k];
+    }
+    out_of_range[i] = out ? 1 : 0;
+}
+
 /* Network output -> conservative state [n][D+2] (AoS), with a free-stream fallback per cell. */
 template <int D>
 __global__ void k_mlp_state(const float* out, const float* tt, double mach, double gamma, const double* uinf, double* W,
-                            int n, int* fallback) {
+                            int n, int* fallback, const int* out_of_range) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double y[4];
     for (int k = 0; k < 4; ++k) y[k] = (double)out[i * 16 + k] * (double)tt[4 + k] + (double)tt[k];
     const double rho = exp(y[0]), u = y[1] * mach, v = y[2] * mach, p = exp(y[3]) / gamma;
-    const bool ok = isfinite(rho) && isfinite(u) && isfinite(v) && isfinite(p) && rho > 1e-6 && p > 1e-8 &&
-                    rho < 1e4 && p < 1e6;
+    const bool ok = !out_of_range[i] && isfinite(rho) && isfinite(u) && isfinite(v) && isfinite(p) && rho > 1e-6 &&
+                    p > 1e-8 && rho < 1e4 && p < 1e6;
     double r = rho, U[3] = {u, v, 0.0}, pr = p;
     if (!ok) {
         atomicAdd(fallback, 1);
@@ -287,6 +323,8 @@ struct cgks_mlp {
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
     std::string err;
+    bool have_range = false;
+    float range[10];            /* training range of the raw features: lo [5], hi [5] */
 };
 
 namespace {
@@ -553,6 +591,30 @@ int cgks_mlp_train_step(cgks_mlp* m, const float* X, const float* Y, int n, floa
  * x, y, distance to the nearest wall-face centre), standardised with fmean /
  * fstd; outputs de-standardised with tmean / tstd; cells whose prediction is
  * non-physical or non-finite fall back to the free stream. */
+/* Raw features of a 2-D context's fine cells into the device array X [n][5]
+ * (stream-ordered on the context's stream, synchronised). */
+static int cell_features(cgks_ctx* c, float* X) {
+    using namespace cgks;
+    const HLevel& H = c->hl[0];
+    std::vector<double> wc;
+    for (const HFace& f : H.faces)
+        if (f.R < 0 && (f.tag == CGKS_TAG_SLIP || f.tag == CGKS_TAG_ISOTHERMAL || f.tag == CGKS_TAG_ADIABATIC)) {
+            wc.push_back(f.xc[0]);
+            wc.push_back(f.xc[1]);
+        }
+    double* dwc = nullptr;
+    if (!wc.empty() && (hipMalloc((void**)&dwc, wc.size() * 8) != hipSuccess ||
+                        hipMemcpy(dwc, wc.data(), wc.size() * 8, hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipFree(dwc);
+        return fail(c, CGKS_EDEVICE, "wall-centre upload failed");
+    }
+    const double lre = c->p.reynolds > 0.0 ? std::log10(c->p.reynolds) : 0.0;
+    k_features<<<nb(H.n, 256), 256, 0, c->stream>>>(c->fine.C, H.n, dwc, (int)wc.size() / 2, c->p.mach, lre, X);
+    const bool ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(c->stream) == hipSuccess;
+    (void)hipFree(dwc);
+    return ok ? CGKS_OK : fail(c, CGKS_EDEVICE, "feature kernel failed");
+}
+
 extern "C" int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, const float* fstd,
                                   const float* tmean, const float* tstd, int* n_fallback) {
     using namespace cgks;
@@ -561,49 +623,40 @@ extern "C" int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, 
     if (c->dim != 2) return fail(c, CGKS_EINVAL, "the warm start is defined for 2-D meshes");
     for (int k = 0; k < 5; ++k)
         if (!(fstd[k] > 0.0f)) return fail(c, CGKS_EINVAL, "feature scales must be positive");
-    const HLevel& H = c->hl[0];
-    const int n = H.n;
-    std::vector<double> wx, wy;
-    for (const HFace& f : H.faces)
-        if (f.R < 0 && (f.tag == CGKS_TAG_SLIP || f.tag == CGKS_TAG_ISOTHERMAL || f.tag == CGKS_TAG_ADIABATIC)) {
-            wx.push_back(f.xc[0]);
-            wy.push_back(f.xc[1]);
-        }
-    const double lre = c->p.reynolds > 0.0 ? std::log10(c->p.reynolds) : 0.0;
-    std::vector<float> X((size_t)n * 5);
-    for (int i = 0; i < n; ++i) {
-        const double x = H.C[2 * i], y = H.C[2 * i + 1];
-        double dmin = wx.empty() ? 0.0 : 1e300;
-        for (size_t k = 0; k < wx.size(); ++k)
-            dmin = std::min(dmin, (x - wx[k]) * (x - wx[k]) + (y - wy[k]) * (y - wy[k]));
-        const double feat[5] = {c->p.mach, lre, x, y, std::sqrt(dmin)};
-        for (int k = 0; k < 5; ++k) X[(size_t)i * 5 + k] = (float)((feat[k] - fmean[k]) / fstd[k]);
+    const int n = c->hl[0].n;
+    float *dX = nullptr, *dt = nullptr, *dms = nullptr, *drg = nullptr;
+    double *du = nullptr, *dW = nullptr;
+    int *dfb = nullptr, *door = nullptr;
+    int rc = CGKS_OK;
+    float ms[10], tt[8];
+    for (int k = 0; k < 5; ++k) {
+        ms[k] = fmean[k];
+        ms[5 + k] = fstd[k];
     }
-    float tt[8];
     for (int k = 0; k < 4; ++k) {
         tt[k] = tmean[k];
         tt[4 + k] = tstd[k];
     }
-    float *dX = nullptr, *dt = nullptr;
-    double *du = nullptr, *dW = nullptr;
-    int* dfb = nullptr;
-    int rc = CGKS_OK;
-    if (hipMalloc((void**)&dX, X.size() * 4) != hipSuccess || hipMalloc((void**)&dt, 8 * 4) != hipSuccess ||
+    if (hipMalloc((void**)&dX, (size_t)n * 5 * 4) != hipSuccess || hipMalloc((void**)&dt, 8 * 4) != hipSuccess ||
+        hipMalloc((void**)&dms, 10 * 4) != hipSuccess || hipMalloc((void**)&drg, 10 * 4) != hipSuccess ||
         hipMalloc((void**)&du, 3 * 8) != hipSuccess || hipMalloc((void**)&dW, (size_t)n * 4 * 8) != hipSuccess ||
-        hipMalloc((void**)&dfb, 4) != hipSuccess)
+        hipMalloc((void**)&dfb, 4) != hipSuccess || hipMalloc((void**)&door, (size_t)n * 4) != hipSuccess)
         rc = fail(c, CGKS_EDEVICE, "device allocation failed");
     if (rc == CGKS_OK) rc = ensure_ws(m, n);
+    if (rc == CGKS_OK) rc = cell_features(c, dX);
     int fb = 0;
     if (rc == CGKS_OK) {
-        bool ok = hipMemcpy(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemcpy(dt, tt, 8 * 4, hipMemcpyHostToDevice) == hipSuccess &&
+        bool ok = hipMemcpy(dt, tt, 8 * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(dms, ms, 10 * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(drg, m->range, 10 * 4, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(du, c->kp.u_inf, 3 * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemset(dfb, 0, 4) == hipSuccess;
         if (ok) {
             hipStream_t keep = m->stream;
             m->stream = c->stream;
+            k_standardise<<<nb(n, 256), 256, 0, c->stream>>>(dX, n, dms, m->have_range ? drg : nullptr, door);
             forward(m, dX, n);
-            k_mlp_state<2><<<nb(n, 256), 256, 0, c->stream>>>(m->out, dt, c->p.mach, c->p.gamma, du, dW, n, dfb);
+            k_mlp_state<2><<<nb(n, 256), 256, 0, c->stream>>>(m->out, dt, c->p.mach, c->p.gamma, du, dW, n, dfb, door);
             m->stream = keep;
             ok = hipMemcpyAsync(&fb, dfb, 4, hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
                  hipStreamSynchronize(c->stream) == hipSuccess;
@@ -613,8 +666,43 @@ extern "C" int cgks_init_from_mlp(cgks_ctx* c, cgks_mlp* m, const float* fmean, 
     if (n_fallback) *n_fallback = fb;
     (void)hipFree(dX);
     (void)hipFree(dt);
+    (void)hipFree(dms);
+    (void)hipFree(drg);
     (void)hipFree(du);
     (void)hipFree(dW);
     (void)hipFree(dfb);
+    (void)hipFree(door);
+    return rc;
+}
+
+extern "C" int cgks_mlp_set_range(cgks_mlp* m, const float* lo, const float* hi) {
+    if (!m) return CGKS_EINVAL;
+    if (!lo || !hi) {
+        m->have_range = false;
+        return CGKS_OK;
+    }
+    for (int k = 0; k < 5; ++k)
+        if (!(lo[k] <= hi[k])) return CGKS_EINVAL;
+    for (int k = 0; k < 5; ++k) {
+        m->range[k] = lo[k];
+        m->range[5 + k] = hi[k];
+    }
+    m->have_range = true;
+    return CGKS_OK;
+}
+
+extern "C" int cgks_mlp_features(cgks_ctx* c, float* X, int mem) {
+    using namespace cgks;
+    if (!c || !X || (mem != CGKS_HOST && mem != CGKS_DEVICE)) return CGKS_EINVAL;
+    if (!c->have_mesh) return fail(c, CGKS_EINVAL, "no mesh");
+    if (c->dim != 2) return fail(c, CGKS_EINVAL, "the warm start is defined for 2-D meshes");
+    const int n = c->hl[0].n;
+    if (mem == CGKS_DEVICE) return cell_features(c, X);
+    float* dX = nullptr;
+    if (hipMalloc((void**)&dX, (size_t)n * 5 * 4) != hipSuccess) return fail(c, CGKS_EDEVICE, "device allocation failed");
+    int rc = cell_features(c, dX);
+    if (rc == CGKS_OK && hipMemcpy(X, dX, (size_t)n * 5 * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(c, CGKS_EDEVICE, "copy of the features failed");
+    (void)hipFree(dX);
     return rc;
 }

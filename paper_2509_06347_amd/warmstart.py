@@ -2,14 +2,17 @@
 
 Data: converged steady solutions produced by the batched V-cycle solver.
 Features per fine cell: Mach, log10 Re, centroid x, y and the distance to the
-nearest wall-face centre (the definition `cgks_init_from_mlp` uses).
+nearest wall-face centre, computed on the device by `cgks_mlp_features` — the
+same kernel `cgks_init_from_mlp` evaluates before inference.
 Targets per cell: log(rho / rho_inf), u / U_inf, v / U_inf, log(p / p_inf).
 Features and targets are standardised with the training set's mean and
 standard deviation.  Training runs on the GPU through `cgks_mlp_train_step`
 (Adam, cosine-decayed learning rate, fixed-order reductions).
 
-Everything numeric runs in the library; this module only prepares arrays,
-draws mini-batch indices and orchestrates solves.
+The features, the network's training and inference and the solves run in
+the library; this module draws problems and mini-batch indices, standardises
+the data (mean and standard deviation of the training set) and transforms
+the converged states into targets.
 """
 from __future__ import annotations
 
@@ -22,23 +25,6 @@ import numpy as np
 from . import cgks
 
 GAMMA = 1.4
-
-
-def wall_centres(mesh):
-    """Centres of the wall faces (slip, isothermal or adiabatic tags)."""
-    wall = np.isin(mesh.btags, (cgks.TAG_SLIP, cgks.TAG_ISOTHERMAL, cgks.TAG_ADIABATIC))
-    return mesh.coords[mesh.bfaces[wall]].mean(axis=1)
-
-
-def features(mesh, centroids, mach, reynolds):
-    """Raw (unstandardised) features [n, 5] of every fine cell."""
-    wc = wall_centres(mesh)
-    d2 = np.full(len(centroids), np.inf)
-    for c in wc:  # wall faces are few; cells many
-        d2 = np.minimum(d2, ((centroids - c) ** 2).sum(axis=1))
-    n = len(centroids)
-    return np.column_stack([np.full(n, mach), np.full(n, math.log10(reynolds)),
-                            centroids[:, 0], centroids[:, 1], np.sqrt(d2)])
 
 
 def targets(W, mach):
@@ -95,8 +81,7 @@ def dataset(problems, solvers, status):
         if st != cgks.OK:
             continue
         W, _, _ = s.get_state()
-        _, C = s.cell_geometry(0)
-        X.append(features(p.mesh, C, p.mach, p.reynolds))
+        X.append(s.mlp_features().astype(np.float64))
         Y.append(targets(W, p.mach))
     return np.concatenate(X), np.concatenate(Y)
 
@@ -107,6 +92,8 @@ class Scaling:
     fstd: np.ndarray
     tmean: np.ndarray
     tstd: np.ndarray
+    flo: np.ndarray = None      # training range of the raw features
+    fhi: np.ndarray = None
 
     @classmethod
     def fit(cls, X, Y):
@@ -114,7 +101,7 @@ class Scaling:
         fs[fs == 0] = 1.0
         ts = Y.std(axis=0)
         ts[ts == 0] = 1.0
-        return cls(X.mean(axis=0), fs, Y.mean(axis=0), ts)
+        return cls(X.mean(axis=0), fs, Y.mean(axis=0), ts, X.min(axis=0), X.max(axis=0))
 
 
 def train(net, X, Y, scaling, steps, batch=16384, lr=1e-3, seed=0, log_every=0):
@@ -143,7 +130,11 @@ def train(net, X, Y, scaling, steps, batch=16384, lr=1e-3, seed=0, log_every=0):
 
 
 def warm_init(net, scaling):
-    """An init(k, solver) for batched_solve that warm-starts from the network."""
+    """An init(k, solver) for batched_solve that warm-starts from the network;
+    cells whose features leave the training range take the free stream."""
+    if scaling.flo is not None:
+        net.set_range(scaling.flo, scaling.fhi)
+
     def init(k, solver):
         net.init_solver(solver, scaling.fmean, scaling.fstd, scaling.tmean, scaling.tstd)
     return init

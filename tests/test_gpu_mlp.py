@@ -184,3 +184,41 @@ def test_warm_start_state_is_physical_and_usable(cg):
     assert np.all(p > 0)
     n = s.vcycle()
     assert np.isfinite(n)
+
+
+def test_device_features_follow_their_definition(cg):
+    """cgks_mlp_features (the one feature kernel behind training data and the
+    warm start): Mach, log10 Re, centroid, distance to the nearest wall-face
+    centre, against the definition evaluated here in FP64."""
+    mesh = sm.annulus(12, 4, jitter=0.1, seed=3, nref=1, wall_tag=sm.ISOTHERMAL)
+    s = cg.Solver(mesh, n_levels=2, mach=0.25, reynolds=35.0)
+    X = s.mlp_features()
+    _, C = s.cell_geometry(0)
+    wall = mesh.btags == sm.ISOTHERMAL
+    wc = mesh.coords[mesh.bfaces[wall]].mean(axis=1)
+    d = np.sqrt(((C[:, None, :] - wc[None, :, :]) ** 2).sum(axis=2).min(axis=1))
+    ref = np.column_stack([np.full(len(C), 0.25), np.full(len(C), np.log10(35.0)), C[:, 0], C[:, 1], d])
+    np.testing.assert_allclose(X, ref, rtol=2e-7, atol=1e-7)
+
+
+def test_warm_start_outside_training_range_falls_back(cg):
+    """A problem whose Mach number lies outside the network's training range
+    starts from the free stream in every cell; inside it, the network is used."""
+    net = cg.MLP(seed=6)
+    s = _solver(cg)
+    s.init_freestream()
+    Wf, _, _ = s.get_state()
+    X = s.mlp_features()
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    lo[0], hi[0] = 0.5, 0.8                    # Mach 0.38 is outside
+    net.set_range(lo, hi)
+    s.set_state(np.zeros_like(Wf))
+    nfb = net.init_solver(s, np.zeros(5), np.full(5, 4.0), np.zeros(4), np.full(4, 0.05))
+    W, _, _ = s.get_state()
+    assert nfb == W.shape[0]
+    np.testing.assert_allclose(W, Wf, rtol=1e-15, atol=1e-15)
+    lo[0], hi[0] = 0.3, 0.5                    # inside
+    net.set_range(lo, hi)
+    nfb = net.init_solver(s, np.zeros(5), np.full(5, 4.0), np.zeros(4), np.full(4, 0.05))
+    assert nfb < W.shape[0]
+    net.set_range(None, None)
