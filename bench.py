@@ -62,6 +62,12 @@ RECON_BYTES_PER_CELL = {
 # kernel source the counters were taken with; absent (null) otherwise.
 TRAFFIC_BYTES = {}
 
+# FP64 operations the flux kernel executes per face Gauss point, from the
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of one launch (64 lanes per
+# wave instruction, FMA counted twice) divided by the launch's Gauss points.
+# Valid only for the flux source the counters were taken with.
+FLUX_FP64_OPS_PER_POINT = {("sphere_euler_mach6_3.1M", "k_flux<3>"): 7219}
+
 
 def workload(name):
     import synthmesh as sm
@@ -172,6 +178,55 @@ def time_to_1e10(cgks, max_cycles, explicit_cap):
         out["gmg_vs_explicit"] = {"explicit": ex, "speedup_plain_fp64": speed,
                                   "note": "explicit = the fine CGKS step alone (one level) from the free stream"}
     return out
+
+
+# ------------------------------------------------------------ batched sweep --
+
+def batch_sweep(cgks, stream, warmup, steps, solve_cycles):
+    """The batched parameter sweep (64 uneven cylinder problems, Mach 0.3-8,
+    Re 1e3-1e5, one disjoint-union hierarchy replayed as one graph, FP32
+    coarse correction, 10-cycle CFL ramp, autotuned launch shapes): V-cycle
+    throughput over all problems, then a solve towards 1e-10 with converged
+    and failed members frozen, reporting each draw's status."""
+    import numpy as np
+    import torch
+    import synthmesh as sm
+    probs = sm.parameter_sweep()
+    solvers = []
+    for mesh, p in probs:
+        s = cgks.Solver(mesh, n_levels=3, precision=cgks.MIXED, cfl_ramp=10, stream=stream.cuda_stream, **p)
+        initial_state(s, mesh, p)
+        solvers.append(s)
+    ncell = sum(m.n_cells for m, _ in probs)
+    batch = cgks.Batch(solvers)
+    batch.autotune()
+    if warmup > 0:
+        batch.run_cycles(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    try:
+        batch.run_cycles(steps)
+        timed_status = "ok"
+    except cgks.CgksError as e:
+        timed_status = f"a member went non-physical ({e.code})"
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    t = time.perf_counter()
+    rc, cycles, status = batch.solve(tol=1e-10, max_cycles=solve_cycles)
+    torch.cuda.synchronize()
+    st = {"converged": int((status == cgks.OK).sum()), "not_converged": int((status == cgks.NOTCONV).sum()),
+          "non_physical": int((status == cgks.ENONPHYS).sum())}
+    return {"workload": "cylinder_sweep_64 (Mach U[0.3, 8], log10 Re U[3, 5], 8,192-131,072 triangles each)",
+            "problems": len(probs), "fine_cells": ncell, "precision": "FP64 residual, FP32 coarse correction",
+            "ms_per_cycle": ms / steps, "value": ncell * steps / (ms / 1e3) / 1e6, "unit": "Mcell·V-cycles/s",
+            "timed_cycles_status": timed_status,
+            "solve": {"tol": 1e-10, "max_cycles": solve_cycles, "seconds": time.perf_counter() - t,
+                      "status_counts": st, "cycles": [int(x) for x in cycles], "status": [int(x) for x in status],
+                      "mach": [p["mach"] for _, p in probs], "reynolds": [p["reynolds"] for _, p in probs],
+                      "note": "Re >= 1e3 cylinder wakes are unsteady: no steady state exists to converge to"}}
 
 
 # ---------------------------------------------------------------- ablations --
@@ -301,6 +356,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--explicit-cap", type=int, default=100000,
                     help="most steps of the explicit-solver comparison (0 skips it)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem sweep")
+    ap.add_argument("--batch-solve-cycles", type=int, default=400)
     ap.add_argument("--ablations", action="store_true",
                     help="print the smoother/relaxation ablation table (one JSON line) instead")
     ap.add_argument("--hyper-cycles", type=int, default=3000)
@@ -348,9 +405,17 @@ def main():
     rb = RECON_BYTES_PER_CELL[d]
     rec = kern["recon"]
     gbs = rb * rec["work_items"] / (rec["avg_ms"] / 1e3) / 1e9
-    roof = {"bound": "hbm", "kernel": f"k_recon2<{d}>", "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, "k_recon2")),
+    roof = {"bound": "hbm", "kernel": f"k_recon<{d}>", "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, f"k_recon<{d}>")),
             "avg_ms": rec["avg_ms"], "work_items": rec["work_items"], "bytes_per_item": rb}
+    # the flux kernel against the FP64 vector peak, from its counted operations
+    fx = kern["flux"]
+    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}>"))
+    if ops:
+        tf = ops * fx["work_items"] / (fx["avg_ms"] / 1e3) / 1e12
+        kern["flux"]["fp64"] = {"bound": "fp64", "achieved": tf, "peak": MI355X_FP64_VECTOR_TFLOPS,
+                                "unit": "TFLOP/s", "frac": tf / MI355X_FP64_VECTOR_TFLOPS,
+                                "ops_per_item": ops, "ops": "executed, from instruction counters"}
 
     # the FP32 coarse correction on the same workload and start
     mixed = cgks.Solver(mesh, n_levels=3, stream=stream.cuda_stream, precision=cgks.MIXED, **params)
@@ -377,6 +442,9 @@ def main():
            "chosen_form": chosen,
            "last_norm": float(hist[-1]) if len(hist) else None}
     del solver
+    if not args.no_batch:
+        print("bench: batched sweep", file=sys.stderr, flush=True)
+        out["batch_sweep"] = batch_sweep(cgks, stream, args.warmup, args.steps, args.batch_solve_cycles)
     if not args.no_ttol:
         print("bench: time to 1e-10", file=sys.stderr, flush=True)
         out["time_to_1e-10"] = time_to_1e10(cgks, args.max_cycles, args.explicit_cap)

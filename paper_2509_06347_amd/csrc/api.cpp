@@ -847,7 +847,7 @@ int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
 extern "C" int cgks_autotune(cgks_ctx* c) {
     TRY(check_level(c, 0));
     /* launch shape of each fine kernel: the fastest candidate at the current state */
-    static const int cand[3][3] = {{32, 64, 0}, {64, 128, 256}, {64, 128, 256}};  /* recon: cells per block */
+    static const int cand[3][3] = {{16, 32, 64}, {64, 128, 256}, {64, 128, 256}};  /* recon: cells per block */
     int best[3] = {c->blk_recon, c->blk_flux, c->blk_gather};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1060,10 +1060,17 @@ int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out) {
         cgks_batch_destroy(B);
         return rc;
     }
+    int* pact;
+    if ((rc = dalloc(c, &pact, n)) || (rc = h2d(c, pact, std::vector<int>(n, 1)))) {
+        cgks_batch_destroy(B);
+        return rc;
+    }
+    m->ws.pactive = pact;
     m->fine.pid = pid;
     m->fine.fpid = fpid;
     m->fine.ptab = dtab;
     m->fine.r2 = r2;
+    m->fine.pact = pact;
     for (int l = 1; l < L; ++l) {
         const HLevel& H = m->hl[l];
         std::vector<int> cp(H.n);
@@ -1075,6 +1082,7 @@ int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out) {
         }
         m->coarse[l - 1].pid = d;
         m->coarse[l - 1].ptab = dtab;
+        m->coarse[l - 1].pact = pact;
     }
     m->ws.nprob = n;
     m->ws.poff = poff;
@@ -1105,6 +1113,7 @@ int cgks_batch_run_cycles(cgks_batch* B, int ncyc, double* history) {
     cgks_ctx* c = B->m;
     const int n = (int)B->probs.size();
     TRY(build_graph(c));
+    TRY(h2d(c, c->ws.pactive, std::vector<int>(n, 1)));   /* every member cycles */
     std::vector<double> h((size_t)n * B->cap);
     int done = 0;
     while (done < ncyc) {
@@ -1120,7 +1129,9 @@ int cgks_batch_run_cycles(cgks_batch* B, int ncyc, double* history) {
         done += k;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
-    return CGKS_OK;
+    int st = 0;
+    HIPCHK(hipMemcpy(&st, c->ws.status, sizeof(int), hipMemcpyDeviceToHost));
+    return st ? CGKS_ENONPHYS : CGKS_OK;
 }
 
 int cgks_batch_solve(cgks_batch* B, double tol, int max_cycles, int* cycles_out, int* status_out) {
@@ -1128,8 +1139,9 @@ int cgks_batch_solve(cgks_batch* B, double tol, int max_cycles, int* cycles_out,
     cgks_ctx* c = B->m;
     const int n = (int)B->probs.size();
     TRY(build_graph(c));
-    std::vector<int> conv(n, -1), bad(n, 0);
+    std::vector<int> conv(n, -1), bad(n, 0), act(n, 1);
     std::vector<double> h((size_t)n * B->cap);
+    TRY(h2d(c, c->ws.pactive, act));
     int done = 0, chunk = 8;
     while (done < max_cycles) {
         const int k = std::min(std::min(chunk, B->cap), max_cycles - done);
@@ -1137,17 +1149,23 @@ int cgks_batch_solve(cgks_batch* B, double tol, int max_cycles, int* cycles_out,
         for (int j = 0; j < k; ++j) HIPCHK(hipGraphLaunch(c->graph, c->stream));
         HIPCHK(hipMemcpyAsync(h.data(), c->ws.history, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        bool all = true;
+        bool all = true, changed = false;
         for (int b = 0; b < n; ++b) {
+            if (!act[b]) continue;
             for (int j = 0; j < k; ++j) {
                 const double v = h[(size_t)b * B->cap + j];
                 if (!std::isfinite(v)) bad[b] = 1;
                 if (conv[b] < 0 && v <= tol) conv[b] = done + j + 1;
             }
             if (conv[b] < 0 && !bad[b]) all = false;
+            else {
+                act[b] = 0;           /* converged or failed: frozen from the next chunk on */
+                changed = true;
+            }
         }
         done += k;
         if (all) break;
+        if (changed) TRY(h2d(c, c->ws.pactive, act));
         chunk = std::min(64, chunk * 2);
     }
     TRY(batch_state(B, false));

@@ -76,6 +76,7 @@ struct FineDev {
     const int *pid, *fpid;
     const double* ptab;
     double* r2;                       /* per-cell (R_rho / V)^2 for per-problem norms */
+    const int* pact;                  /* per-problem "still cycling" flags (null: every cell cycles) */
 };
 
 struct CoarseDev {
@@ -90,6 +91,7 @@ struct CoarseDev {
     int *child_off, *child;           /* CSR of finer internal indices */
     const int* pid;                   /* batched solves: problem id per cell (else null) */
     const double* ptab;
+    const int* pact;                  /* per-problem "still cycling" flags (null: every cell cycles) */
 };
 
 /* Per-problem entries of a batched solve (the fields that may differ). */
@@ -108,6 +110,7 @@ struct Workspace {
     int nprob = 0;
     int* poff = nullptr;              /* fine-cell offsets of the problems, nprob+1 */
     double* ptab = nullptr;           /* per-problem parameter table */
+    int* pactive = nullptr;           /* per-problem flags: 1 = cycle, 0 = frozen (converged or failed) */
 };
 
 /* Scalar parameters as seen by the kernels. */

@@ -2,15 +2,14 @@
  * gfx950 kernels of the multigrid CGKS V-cycle.
  *
  * Fine level (third-order CGKS, Secs. 2-3):
- *   k_recon   one thread per cell: time step, compact reconstruction (p^2 by
- *             the precomputed constrained least-squares operator, alpha-scaled
- *             Green-Gauss p^1, nonlinear weights), positivity guard, and the
- *             reconstructed state and gradient at every Gauss point of the
- *             cell's faces (plus the ghost state on boundary faces), written
- *             into face-ordered Gauss-point slots.
- *   k_flux    one thread per (face, Gauss point): BGK flux, state at t = dt,
- *             DF factor.  Gauss-point-major layout: consecutive threads read
- *             consecutive faces.
+ *   k_recon   per block of cells, in LDS-staged stages: time steps, compact
+ *             reconstruction (p^2 by the precomputed constrained
+ *             least-squares operator, alpha-scaled Green-Gauss p^1,
+ *             nonlinear weights), positivity guard; writes each cell's
+ *             polynomial record.
+ *   k_flux    one lane per (face, Gauss point): both cells' polynomials at
+ *             the point, BGK flux, state at t = dt, DF factor; the face's
+ *             lanes sum their contributions into a per-face record.
  *   k_gather  one thread per cell: residual, DF-scaled evolved slopes, DF;
  *             optionally the explicit update of Eq. smo and the residual-norm
  *             partial sums.
@@ -47,6 +46,13 @@ __device__ __forceinline__ KParams localize(const KParams& kp, const double* pta
         k.u_inf[2] = t[6];
     }
     return k;
+}
+
+/* Whether the problem that owns item idx still cycles: in a batched solve the
+ * members that have converged or failed are frozen (their kernels' work is
+ * skipped); a single problem always cycles. */
+__device__ __forceinline__ bool active(const int* pact, const int* pid, int idx) {
+    return !pact || pact[pid[idx]] != 0;
 }
 
 /* Implicit CFL of the LU-SGS in the current V-cycle: cfl_imp, or with a ramp of
@@ -167,191 +173,269 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
     }
 }
 
-/* Reconstruction in two phases per block of `cells` cells (blockDim = cells x
- * faces x Gauss points).  Phase 1, one thread per (cell, component): the p^2
- * coefficients from the operator, the alpha-scaled Green-Gauss gradient and
- * the nonlinear weights, into LDS; the component-0 thread also forms the local
- * time steps.  Phase 2, one thread per (cell, face slot, Gauss point): the
- * combined polynomial's value at its point, for the cell's positivity guard
- * (an LDS flag over its points).  Then the block writes each cell's polynomial
- * record (coefficients, zeroed when the guard holds so that the cell is
- * constant; cell averages; basis means; centroid; 1/h), contiguous per cell,
- * which the flux kernel evaluates at its Gauss points.  Per cell and component
- * the arithmetic is that of a one-thread-per-cell evaluation. */
-constexpr int RMAXC = 64;   /* most cells per reconstruction block */
+/* Per-block LDS of the reconstruction: for each field, one double per cell of
+ * the block (stride cells + 1, so that the record writes, which walk the
+ * fields of one cell, spread over the banks). */
+template <int D>
+struct RLds {
+    using S = Shape<D>;
+    static constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NK = S::NK;
+    static constexpr int WN = 0;                     /* [NS][NV] neighbour averages (ghost states on boundary faces) */
+    static constexpr int GN = WN + NS * NV;          /* [NS][NV][D] neighbour gradients */
+    static constexpr int W0 = GN + NS * NV * D;      /* [NV] cell averages */
+    static constexpr int MEAN = W0 + NV;             /* [NQ] basis means */
+    static constexpr int GEO = MEAN + NQ;            /* [NS][1 + D] face area, outward unit normal */
+    static constexpr int CEL = GEO + NS * (1 + D);   /* volume, h, DF factor */
+    static constexpr int COEF = CEL + 3;             /* [NV][NK] p^2 part, Green-Gauss part */
+    static constexpr int FIELDS = COEF + NV * NK;
+    /* bytes for `cells` cells: the fields, then per-cell neighbour flags [NS] and the guard flag */
+    static constexpr size_t bytes(int cells) {
+        return (size_t)FIELDS * (cells + 1) * sizeof(double) + (size_t)(NS + 1) * cells * sizeof(int);
+    }
+};
+
+/* Reconstruction of a block of `cells` cells (blockDim = cells x faces x Gauss
+ * points), in stages separated by block barriers, each with its own mapping of
+ * threads to work so that every stage keeps most lanes busy and issues its
+ * global loads together:
+ *   1. (cell, face slot, component): the cell's and its neighbours' data into
+ *      LDS (cell and neighbour averages, neighbour gradients, basis means,
+ *      face geometry, V, h, DF factor);
+ *   2. (cell, face slot) on boundary faces: the ghost averages; and
+ *      (cell, p^2 basis function k): row k of the constrained least-squares
+ *      operator (Sec. 3.1) applied to the neighbour differences and gradients
+ *      of every component;
+ *   3. (cell, component): the DF-scaled Green-Gauss p^1, the smoothness
+ *      indicators and nonlinear weights (Sec. 3.2), the combined
+ *      coefficients; component 0 also forms the local time steps;
+ *   4. (cell, face slot, Gauss point): the combined polynomial's value at the
+ *      point, for the cell's positivity guard (an LDS flag over its points).
+ * The block then writes each cell's polynomial record (coefficients, zeroed
+ * when the guard holds so that the cell is constant; cell averages; basis
+ * means; centroid; 1/h), contiguous per cell, which the flux kernel
+ * evaluates at its Gauss points.  Per cell and component the arithmetic, and
+ * its order, is that of a one-thread-per-cell evaluation. */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
 template <int D>
-__global__ void __launch_bounds__(RTHREADS) k_recon2(FineDev f, KParams kp0, int cells) {
+__global__ void __launch_bounds__(RTHREADS) k_recon(FineDev f, KParams kp0, int cells) {
     using S = Shape<D>;
-    constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NC = S::NC, NCOL = S::NCOL;
-    constexpr int NK = NQ + D;
-    __shared__ double coef[NV * NK][RMAXC];
-    __shared__ double wsh[NV][RMAXC];      /* cell states, for phase 2 */
-    __shared__ double msh[NQ][RMAXC];      /* basis means, for phase 2 */
-    __shared__ int bad[RMAXC];
-    const int t = threadIdx.x;
-    const int n = f.n, nf = f.nf;
+    using L = RLds<D>;
+    constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NCOL = S::NCOL, NK = S::NK;
+    extern __shared__ double lds[];
+    const int cs = cells + 1;
+    int* nbf = reinterpret_cast<int*>(lds + (size_t)L::FIELDS * cs);   /* [NS][cells] neighbour, < 0 on boundaries */
+    int* bad = nbf + NS * cells;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int n = f.n;
     const int i0 = blockIdx.x * cells;
+#define FLD(field, cl) lds[(field) * cs + (cl)]
 
-    /* ---- phase 1: (cell, component) ---- */
-    if (t < cells * NV) {
-        const int cl = t % cells, q = t / cells;
+    /* ---- 1: loads, (cell, slot, component) ---- */
+    for (int u = t; u < cells * NS * NV; u += nt) {
+        const int cl = u % cells, r = u / cells, s = r % NS, q = r / NS;
         const int i = i0 + cl;
-        if (q == 0) bad[cl] = 0;
-        if (i < n) {
-            const KParams kp = localize(kp0, f.ptab, f.pid, i);
-            double W0[NV];
+        if (i >= n || !active(f.pact, f.pid, i)) continue;
+        const int nb = f.slot_nbr[s * n + i];
+        double w = 0.0, g[D];
+        if (nb >= 0) {
+            w = f.W[q * n + nb];
 #pragma unroll
-            for (int r = 0; r < NV; ++r) W0[r] = f.W[r * n + i];
-            const double V = f.V[i], h = f.h[i], al = f.alpha[i];
-            int nbr[NS];
-            double nout[NS][D], Sf[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                nbr[s] = f.slot_nbr[s * n + i];
-                Sf[s] = f.slot_S[s * n + i];
-#pragma unroll
-                for (int d = 0; d < D; ++d) nout[s][d] = f.slot_n[(d * NS + s) * n + i];
-            }
-            if (q == 0) {
-                Prim P;
-                primitive<D>(kp, W0, P);
-                const double c = sqrt(kp.gamma * P.p / P.rho);
-                double lam = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    double un = 0.0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) un += P.U[d] * nout[s][d];
-                    lam += Sf[s] * (fabs(un) + c);
-                    s2 += Sf[s] * Sf[s];
-                }
-                if (kp.reynolds > 0.0)
-                    lam += fmax(4.0 / 3.0, kp.gamma / kp.prandtl) * sutherland(kp, P.p / P.rho) / P.rho * s2 / V;
-                f.dt[i] = kp.cfl_exp * V / lam;
-                f.dti[i] = implicit_cfl(kp) * V / lam;
-            }
-            /* component q of the neighbour averages (ghost averages on boundary faces) */
-            double Wq[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (nbr[s] >= 0) {
-                    Wq[s] = f.W[q * n + nbr[s]];
-                } else {
-                    double Wg[NV];
-                    ghost_state<D, false>(kp, f.slot_tag[s * n + i], W0, nullptr, nout[s], Wg, nullptr);
-                    Wq[s] = Wg[q];
-                }
-            }
-            double mean[NQ];
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) mean[k] = f.mean0[k * n + i];
-            wsh[q][cl] = W0[q];
-            for (int k = q; k < NQ; k += NV) msh[k][cl] = mean[k];
-            double a[NQ];
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) a[k] = 0.0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (nbr[s] < 0) continue;
-                const double dq = Wq[s] - W0[q];
-                double gs[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) gs[d] = f.grad[(q * D + d) * n + nbr[s]];
-#pragma unroll
-                for (int k = 0; k < NQ; ++k) {
-                    const double* o = f.op + (size_t)(k * NCOL + s * (1 + D)) * n + i;
-                    double acc = o[0] * dq;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) acc += o[(size_t)(1 + d) * n] * gs[d];
-                    a[k] += acc;
-                }
-            }
-            double g[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) g[d] = 0.0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const double avg = (Wq[s] + W0[q]) / (2.0 * V);
-#pragma unroll
-                for (int d = 0; d < D; ++d) g[d] += avg * Sf[s] * nout[s][d];
-            }
-            double gg = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                g[d] *= al * h;
-                gg += g[d] * g[d];
-            }
-            const double b0 = beta_large<D>(a, mean);
-            const double b1 = gg;
-            const double tz = fabs(b0 - b1);
-            const double t0 = tz / (b0 + kp.eps), t1 = tz / (b1 + kp.eps);
-            const double w0 = kp.g_large * (1.0 + t0 * t0), w1 = kp.g_small * (1.0 + t1 * t1);
-            const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
-            const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) coef[q * NK + k][cl] = cp2 * a[k];
-#pragma unroll
-            for (int d = 0; d < D; ++d) coef[q * NK + NQ + d][cl] = cp1 * g[d];
+            for (int d = 0; d < D; ++d) g[d] = f.grad[(q * D + d) * n + nb];
         }
+        if (q == 0) nbf[s * cells + cl] = nb;
+        if (s == 0) FLD(L::W0 + q, cl) = f.W[q * n + i];
+        if (q == 0) FLD(L::GEO + s * (1 + D), cl) = f.slot_S[s * n + i];
+        else if (q <= D) FLD(L::GEO + s * (1 + D) + q, cl) = f.slot_n[((q - 1) * NS + s) * n + i];
+        const int lin = s * NV + q;
+        if (lin < NQ) FLD(L::MEAN + lin, cl) = f.mean0[lin * n + i];
+        else if (lin == NQ) FLD(L::CEL, cl) = f.V[i];
+        else if (lin == NQ + 1) FLD(L::CEL + 1, cl) = f.h[i];
+        else if (lin == NQ + 2) FLD(L::CEL + 2, cl) = f.alpha[i];
+        if (nb >= 0) {
+            FLD(L::WN + s * NV + q, cl) = w;
+#pragma unroll
+            for (int d = 0; d < D; ++d) FLD(L::GN + (s * NV + q) * D + d, cl) = g[d];
+        }
+    }
+    for (int u = t; u < cells; u += nt) bad[u] = 0;
+    __syncthreads();
+
+    /* ---- 2: ghost averages of boundary faces, (cell, slot); operator rows,
+     * (cell, k), which read only the interior faces' entries ---- */
+    for (int u = t; u < cells * NS; u += nt) {
+        const int cl = u % cells, s = u / cells;
+        const int i = i0 + cl;
+        if (i >= n || nbf[s * cells + cl] >= 0 || !active(f.pact, f.pid, i)) continue;
+        const KParams kp = localize(kp0, f.ptab, f.pid, i);
+        double W0[NV], nout[D], Wg[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) W0[q] = FLD(L::W0 + q, cl);
+#pragma unroll
+        for (int d = 0; d < D; ++d) nout[d] = FLD(L::GEO + s * (1 + D) + 1 + d, cl);
+        ghost_state<D, false>(kp, f.slot_tag[s * n + i], W0, nullptr, nout, Wg, nullptr);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) FLD(L::WN + s * NV + q, cl) = Wg[q];
+    }
+    for (int u = t; u < cells * NQ; u += nt) {
+        const int cl = u % cells, k = u / cells;
+        const int i = i0 + cl;
+        if (i >= n || !active(f.pact, f.pid, i)) continue;
+        double o[NS][1 + D];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c <= D; ++c) o[s][c] = f.op[(size_t)(k * NCOL + s * (1 + D) + c) * n + i];
+        double a[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) a[q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (nbf[s * cells + cl] < 0) continue;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double dq = FLD(L::WN + s * NV + q, cl) - FLD(L::W0 + q, cl);
+                double acc = o[s][0] * dq;
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc += o[s][1 + d] * FLD(L::GN + (s * NV + q) * D + d, cl);
+                a[q] += acc;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) FLD(L::COEF + q * NK + k, cl) = a[q];
     }
     __syncthreads();
 
-    /* ---- phase 2: (cell, slot, Gauss point).  Triangles: slot fastest, so that
-     * a wave's stores of one component at one Gauss point are contiguous.
-     * Tetrahedra: cell fastest (slot-fastest lanes measured 1.8x slower). ---- */
-    int s, cl, k;
-    if constexpr (D == 2) {
-        s = t % NS;
-        cl = (t / NS) % cells;
-        k = t / (NS * cells);
-    } else {
-        cl = t % cells;
-        s = (t / cells) / NG;
-        k = (t / cells) - s * NG;
-    }
-    const int j = s * NG + k;
-    const int i = i0 + cl;
-    const bool live = i < n && k < NG;
-    double Wx[NV], X[3];
-    if (live) {
-        double phi[NQ], dphi[NQ][3];
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            X[d] = f.slot_X[D == 2 ? ((size_t)(k * D + d) * n + i) * NS + s : ((size_t)(k * D + d) * NS + s) * n + i];
-        basis_at<D>(X, phi, dphi);
-        double pm[NQ];
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) pm[m] = phi[m] - msh[m][cl];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double v = wsh[q][cl];
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) v += coef[q * NK + m][cl] * pm[m];
-#pragma unroll
-            for (int d = 0; d < D; ++d) v += coef[q * NK + NQ + d][cl] * X[d];
-            Wx[q] = v;
-        }
+    /* ---- 3: weights, (cell, component) ---- */
+    for (int u = t; u < cells * NV; u += nt) {
+        const int cl = u % cells, q = u / cells;
+        const int i = i0 + cl;
+        if (i >= n || !active(f.pact, f.pid, i)) continue;
         const KParams kp = localize(kp0, f.ptab, f.pid, i);
-        Prim P;
-        primitive<D>(kp, Wx, P);
-        if (!(P.rho > 0.0 && P.p > 0.0)) atomicOr(&bad[cl], 1);
+        const double V = FLD(L::CEL, cl), h = FLD(L::CEL + 1, cl), al = FLD(L::CEL + 2, cl);
+        double W0[NV], Sf[NS], nout[NS][D];
+#pragma unroll
+        for (int r = 0; r < NV; ++r) W0[r] = FLD(L::W0 + r, cl);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            Sf[s] = FLD(L::GEO + s * (1 + D), cl);
+#pragma unroll
+            for (int d = 0; d < D; ++d) nout[s][d] = FLD(L::GEO + s * (1 + D) + 1 + d, cl);
+        }
+        if (q == 0) {
+            Prim P;
+            primitive<D>(kp, W0, P);
+            const double c = sqrt(kp.gamma * P.p / P.rho);
+            double lam = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double un = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) un += P.U[d] * nout[s][d];
+                lam += Sf[s] * (fabs(un) + c);
+                s2 += Sf[s] * Sf[s];
+            }
+            if (kp.reynolds > 0.0)
+                lam += fmax(4.0 / 3.0, kp.gamma / kp.prandtl) * sutherland(kp, P.p / P.rho) / P.rho * s2 / V;
+            f.dt[i] = kp.cfl_exp * V / lam;
+            f.dti[i] = implicit_cfl(kp) * V / lam;
+        }
+        /* component q of the neighbour averages (ghost averages on boundary faces) */
+        double Wq[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Wq[s] = FLD(L::WN + s * NV + q, cl);
+        double a[NQ], mean[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            a[k] = FLD(L::COEF + q * NK + k, cl);
+            mean[k] = FLD(L::MEAN + k, cl);
+        }
+        double g[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) g[d] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double avg = (Wq[s] + W0[q]) / (2.0 * V);
+#pragma unroll
+            for (int d = 0; d < D; ++d) g[d] += avg * Sf[s] * nout[s][d];
+        }
+        double gg = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            g[d] *= al * h;
+            gg += g[d] * g[d];
+        }
+        const double b0 = beta_large<D>(a, mean);
+        const double b1 = gg;
+        const double tz = fabs(b0 - b1);
+        const double t0 = tz / (b0 + kp.eps), t1 = tz / (b1 + kp.eps);
+        const double w0 = kp.g_large * (1.0 + t0 * t0), w1 = kp.g_small * (1.0 + t1 * t1);
+        const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
+        const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) FLD(L::COEF + q * NK + k, cl) = cp2 * a[k];
+#pragma unroll
+        for (int d = 0; d < D; ++d) FLD(L::COEF + q * NK + NQ + d, cl) = cp1 * g[d];
     }
     __syncthreads();
-    if (live && j == 0 && bad[cl]) atomicAdd(f.guard, 1ull);
+
+    /* ---- 4: positivity guard, (cell, slot, Gauss point).  Triangles: slot
+     * fastest; tetrahedra: cell fastest (slot-fastest lanes measured 1.8x
+     * slower). ---- */
+    {
+        int s, cl, k;
+        if constexpr (D == 2) {
+            s = t % NS;
+            cl = (t / NS) % cells;
+            k = t / (NS * cells);
+        } else {
+            cl = t % cells;
+            s = (t / cells) / NG;
+            k = (t / cells) - s * NG;
+        }
+        const int i = i0 + cl;
+        if (i < n && k < NG && active(f.pact, f.pid, i)) {
+            double X[3], phi[NQ], dphi[NQ][3], Wx[NV];
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                X[d] = f.slot_X[D == 2 ? ((size_t)(k * D + d) * n + i) * NS + s
+                                       : ((size_t)(k * D + d) * NS + s) * n + i];
+            basis_at<D>(X, phi, dphi);
+            double pm[NQ];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) pm[m] = phi[m] - FLD(L::MEAN + m, cl);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                double v = FLD(L::W0 + q, cl);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) v += FLD(L::COEF + q * NK + m, cl) * pm[m];
+#pragma unroll
+                for (int d = 0; d < D; ++d) v += FLD(L::COEF + q * NK + NQ + d, cl) * X[d];
+                Wx[q] = v;
+            }
+            const KParams kp = localize(kp0, f.ptab, f.pid, i);
+            Prim P;
+            primitive<D>(kp, Wx, P);
+            if (!(P.rho > 0.0 && P.p > 0.0)) atomicOr(&bad[cl], 1);
+        }
+    }
+    __syncthreads();
+    for (int u = t; u < cells; u += nt)
+        if (i0 + u < n && bad[u] && active(f.pact, f.pid, i0 + u)) atomicAdd(f.guard, 1ull);
     /* the cells' polynomial records, written contiguously by the whole block */
     constexpr int NPR = S::NPR;
     const int ncell = min(cells, n - i0);
-    for (int e = t; e < ncell * NPR; e += blockDim.x) {
+    for (int e = t; e < ncell * NPR; e += nt) {
         const int c2 = e / NPR, jj = e - c2 * NPR, ii = i0 + c2;
+        if (!active(f.pact, f.pid, ii)) continue;
         double v = 0.0;
-        if (jj < S::REC_W) v = bad[c2] ? 0.0 : coef[jj][c2];
-        else if (jj < S::REC_MEAN) v = wsh[jj - S::REC_W][c2];
-        else if (jj < S::REC_C) v = msh[jj - S::REC_MEAN][c2];
+        if (jj < S::REC_W) v = bad[c2] ? 0.0 : FLD(L::COEF + jj, c2);
+        else if (jj < S::REC_MEAN) v = FLD(L::W0 + jj - S::REC_W, c2);
+        else if (jj < S::REC_C) v = FLD(L::MEAN + jj - S::REC_MEAN, c2);
         else if (jj < S::REC_IH) v = f.C[(size_t)(jj - S::REC_C) * n + ii];
-        else if (jj == S::REC_IH) v = 1.0 / f.h[ii];
+        else if (jj == S::REC_IH) v = 1.0 / FLD(L::CEL + 1, c2);
         f.poly[(size_t)ii * NPR + jj] = v;
     }
+#undef FLD
 }
 
 /* Value and gradient of every component of a cell's combined polynomial at
@@ -405,7 +489,7 @@ __global__ void __launch_bounds__(FTHREADS) k_flux(FineDev f, KParams kp0) {
     const int k = lane % NG, lf = lane / NG;
     const long fcl = wv * FPW + lf;
     const int nf = f.nf;
-    const bool live = lf < FPW && fcl < nf;
+    const bool live = lf < FPW && fcl < nf && active(f.pact, f.fpid, (int)fcl);
     const int fc = live ? (int)fcl : 0;
     double F[NV], G[NV], a = 1.0;
 #pragma unroll
@@ -525,7 +609,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = f.n, nf = f.nf;
     double contrib = 0.0;
-    if (i < n) {
+    if (i < n && active(f.pact, f.pid, i)) {
         double R[NV], Gs[NV][D], a = 1.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
@@ -576,6 +660,13 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
                 finite = finite && isfinite(dW[q]);
             }
             const double fr = update_fraction<D>(Wo, dW, kp.update_limit);
+            /* every load before the first store: a load issued after a store
+             * waits for the store to complete */
+            double go[NV][D];
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int d = 0; d < D; ++d) go[q][d] = f.grad[(q * D + d) * n + i];
             if (keep) {
 #pragma unroll
                 for (int q = 0; q < NV; ++q) {
@@ -588,10 +679,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
                 Wn[q] = fr > 0.0 ? Wo[q] + fr * dW[q] : Wo[q];
                 f.W[q * n + i] = Wn[q];
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const double go = f.grad[(q * D + d) * n + i];
-                    f.grad[(q * D + d) * n + i] = go + th * (sc * Gs[q][d] - go);
-                }
+                for (int d = 0; d < D; ++d) f.grad[(q * D + d) * n + i] = go[q][d] + th * (sc * Gs[q][d] - go[q][d]);
             }
             f.alpha[i] = a;
             Prim P;
@@ -651,7 +739,7 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
-    if (I >= n) return;
+    if (I >= n || !active(c.pact, c.pid, I)) return;
     const KParams kp = localize(kp0, c.ptab, c.pid, I);
     double W[NV];
 #pragma unroll
@@ -747,7 +835,7 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
     const int tx = threadIdx.x, s = threadIdx.y;
     const int I = blockIdx.x * SCELLS + tx;
     const int n = c.n;
-    const bool live = I < n;
+    const bool live = I < n && active(c.pact, c.pid, I);
     const KParams kp = localize(kp0, c.ptab, c.pid, live ? I : 0);
     double W[NV];
     Prim P;
@@ -824,15 +912,16 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
     if (kp.reynolds > 0.0) lam += visc * sutherland(kp, P.p / P.rho) / P.rho * s2 / c.V[I];
     const double V = c.V[I];
     const double dte = kp.cfl_exp * V / lam, dti = implicit_cfl(kp) * V / lam;
-    c.dte[I] = dte;
-    c.dti[I] = dti;
+    /* every load before the first store (a load issued after a store waits for it) */
     double rhs[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) rhs[q] = Res[q] + c.F[q * n + I];
     if (mode == COARSE_RHS) fixed_factor_rhs<NV, T>(kp, c, I, V, dti, rhs);
+    const double Dd = lusgs_diagonal(kp, c.alpha[I], V, dti, dte, sr);
+    c.dte[I] = dte;
+    c.dti[I] = dti;
 #pragma unroll
     for (int q = 0; q < NV; ++q) c.rhs[q * n + I] = rhs[q];
-    const double Dd = lusgs_diagonal(kp, c.alpha[I], V, dti, dte, sr);
     c.D[I] = Dd;
     if (I < hi1) {
         T* dW = reinterpret_cast<T*>(c.dW);
@@ -912,7 +1001,7 @@ __global__ void __launch_bounds__(CBLOCK) k_lusgs(CoarseDev c, KParams kp, int l
     constexpr int NV = D + 2;
     const int I = lo + blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
-    if (I >= hi) return;
+    if (I >= hi || !active(c.pact, c.pid, I)) return;
     T* dW = reinterpret_cast<T*>(c.dW);
     const T* rr = reinterpret_cast<const T*>(c.r);
     T acc[NV];
@@ -955,7 +1044,7 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams 
     const int tx = threadIdx.x, s = threadIdx.y;
     const int I = lo + blockIdx.x * SCELLS + tx;
     const int n = c.n;
-    const bool live = I < hi;
+    const bool live = I < hi && active(c.pact, c.pid, I);
     T* dW = reinterpret_cast<T*>(c.dW);
     T x[NV];
 #pragma unroll
@@ -990,27 +1079,23 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams 
         for (int q = 0; q < NV; ++q) acc[q] += part[q][k][tx];
     const T a = (T)relax_weight(kp, c.alpha[I]);
     const T Di = (T)c.D[I];
+    /* every load before the first store (a load issued after a store waits for it) */
+    T prev[NV];
+    double W[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) prev[q] = fwd ? (T)c.rhs[q * n + I] : dW[q * n + I];
+    if (Wout)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) W[q] = c.W[q * n + I];
     double dWd[NV];
-    if (fwd) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const T d = ((T)c.rhs[q * n + I] - (T)0.5 * a * acc[q]) / Di;
-            dW[q * n + I] = d;
-            dWd[q] = (double)d;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const T d = dW[q * n + I] - (T)0.5 * a * acc[q] / Di;
-            dW[q * n + I] = d;
-            dWd[q] = (double)d;
-        }
+    for (int q = 0; q < NV; ++q) {
+        const T d = fwd ? (prev[q] - (T)0.5 * a * acc[q]) / Di : prev[q] - (T)0.5 * a * acc[q] / Di;
+        dW[q * n + I] = d;
+        dWd[q] = (double)d;
     }
     /* the cell's correction is final: write its new state into the other buffer */
     if (Wout) {
-        double W[NV];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) W[q] = c.W[q * n + I];
         const double th = update_fraction<D>(W, dWd, kp.update_limit);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Wout[q * n + I] = th > 0.0 ? W[q] + th * dWd[q] : W[q];
@@ -1025,7 +1110,7 @@ __global__ void __launch_bounds__(CBLOCK) k_restrict(CoarseDev c, const double* 
     constexpr int NV = D + 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = c.n;
-    if (I >= n) return;
+    if (I >= n || !active(c.pact, c.pid, I)) return;
     double w[NV], amin = 1.0e300;
     T r[NV];
 #pragma unroll
@@ -1067,6 +1152,7 @@ __global__ void __launch_bounds__(CBLOCK) k_prolong(CoarseDev c, double* Wf, con
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nfine) return;
     const int I = c.parent[i];
+    if (!active(c.pact, c.pid, I)) return;
     const int n = c.n;
     const T a = df ? (T)af[i] : (T)1;
     double W[NV], dW[NV];
@@ -1086,11 +1172,12 @@ __global__ void __launch_bounds__(CBLOCK) k_prolong(CoarseDev c, double* Wf, con
 
 /* Coarse LU-SGS update W += theta dW per cell (dW in T). */
 template <int D, class T>
-__global__ void __launch_bounds__(CBLOCK) k_coarse_add(double* Wc, const double* dWraw, int n, double kappa) {
+__global__ void __launch_bounds__(CBLOCK) k_coarse_add(double* Wc, const double* dWraw, int n, double kappa,
+                                                     const int* pid, const int* pact) {
     constexpr int NV = D + 2;
     const T* dWc = reinterpret_cast<const T*>(dWraw);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || !active(pact, pid, i)) return;
     double W[NV], dW[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -1134,7 +1221,7 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
         /* block = cells per block x faces x Gauss points */
         using S = Shape<D>;
         const int cells = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
-        k_recon2<D><<<blocks(f.n, cells), cells * S::NS * S::NG, 0, st>>>(f, c->kp, cells);
+        k_recon<D><<<blocks(f.n, cells), cells * S::NS * S::NG, RLds<D>::bytes(cells), st>>>(f, c->kp, cells);
     } else if (which == 1) {
         /* 64 / NG faces per wave */
         const int b = block ? block : c->blk_flux;
@@ -1274,11 +1361,11 @@ void launch_coarse_update(cgks_ctx* c, int level) {
     const int nb = cblk(L.n);
     const double kap = c->kp.update_limit;
     if (c->dim == 2) {
-        if (mx) k_coarse_add<2, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
-        else k_coarse_add<2, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        if (mx) k_coarse_add<2, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap, L.pid, L.pact);
+        else k_coarse_add<2, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap, L.pid, L.pact);
     } else {
-        if (mx) k_coarse_add<3, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
-        else k_coarse_add<3, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap);
+        if (mx) k_coarse_add<3, float><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap, L.pid, L.pact);
+        else k_coarse_add<3, double><<<nb, CBLOCK, 0, c->stream>>>(L.W, L.dW, L.n, kap, L.pid, L.pact);
     }
 }
 

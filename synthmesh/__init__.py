@@ -208,6 +208,26 @@ def quad_grid_graph(nx, ny):
     return np.array(xadj, dtype=np.int32), np.array(adj, dtype=np.int32)
 
 
+C4_SHAPES = ((32, 8), (64, 8), (64, 16), (128, 16), (128, 32))
+
+
+def parameter_sweep(n=64, seed=4, mesh_seed0=4000):
+    """The batched parameter sweep: n cylinder annuli whose coarsest (N_theta,
+    N_r) is drawn uniformly from C4_SHAPES (8,192 to 131,072 fine triangles
+    after two refinements; jitter 0.1, mesh seed mesh_seed0 + b, isothermal
+    wall), each with its own Mach ~ U[0.3, 8] and log10 Re ~ U[3, 5] (one
+    generator, seeded with `seed`, draws the shapes, then the flows).
+    Returns [(mesh, flow parameters)]."""
+    rng = np.random.default_rng(seed)
+    shapes = [C4_SHAPES[int(k)] for k in rng.integers(0, len(C4_SHAPES), size=n)]
+    flows = draw_flow_params(seed, n)
+    out = []
+    for b, ((nt, nr), (mach, re)) in enumerate(zip(shapes, flows)):
+        mesh = annulus(nt, nr, jitter=0.1, seed=mesh_seed0 + b, nref=2, wall_tag=ISOTHERMAL)
+        out.append((mesh, dict(mach=mach, reynolds=re, prandtl=0.72, wall_T_ratio=1.0)))
+    return out
+
+
 def draw_flow_params(seed, n, mach=(0.3, 8.0), log10_re=(3.0, 5.0)):
     """Parameter-sweep draws: Mach ~ U[mach], log10(Re) ~ U[log10_re]."""
     rng = np.random.default_rng(seed)

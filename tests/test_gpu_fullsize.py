@@ -42,7 +42,7 @@ def test_fullsize_fine_residual_parity(tuned, orc):
     scale = np.abs(Ro).max()
     err = np.abs(Rg - Ro).max()
     print(f"residual: max |dR| / max |R| = {err / scale:.2e}", flush=True)
-    assert err <= 1e-11 * scale
+    assert err <= 1e-12 * scale
     np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
     # alpha reaches ~1e-10 in the shock layer; its relative error is about twice
     # that of the jump ratios it is built from
@@ -62,9 +62,13 @@ def test_fullsize_vcycle_parity(tuned, orc):
     Wg, gg, ag = g.get_state()
     Wo, go, ao = o.get_state()
     assert np.all(np.isfinite(Wg))
-    assert np.abs(Wg - Wo).max() <= 1e-8 * np.abs(Wo).max()
-    assert np.abs(gg - go).max() <= 1e-7 * np.abs(go).max()
-    np.testing.assert_allclose(ag, ao, rtol=0, atol=1e-6)
+    werr = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    gerr = np.abs(gg - go).max() / np.abs(go).max()
+    aerr = np.abs(ag - ao).max()
+    print(f"V-cycle state {werr:.2e}, slopes {gerr:.2e}, DF {aerr:.2e} (absolute)", flush=True)
+    assert werr <= 1e-11
+    assert gerr <= 1e-11
+    assert aerr <= 1e-10
     # prolongation corrections limited by the update safeguard in this cycle
     assert g.stats()[1] - sg0 == o.stats()[1] - so0
 

@@ -91,7 +91,8 @@ def test_fine_residual_parity_3d(cg, orc, case):
     Rg, gg, ag = g.residual(0)
     Ro, go, ao = o.residual(0)
     scale = np.abs(Ro).max()
-    assert np.abs(Rg - Ro).max() <= 1e-11 * scale, np.abs(Rg - Ro).max() / scale
+    print(f"residual: max |dR| / max |R| = {np.abs(Rg - Ro).max() / scale:.2e}", flush=True)
+    assert np.abs(Rg - Ro).max() <= 1e-12 * scale
     np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
     np.testing.assert_allclose(ag, ao, rtol=1e-12, atol=1e-13)
     dg, _ = g.time_steps(0)
@@ -149,7 +150,10 @@ def test_sphere_setup_and_residual_parity(cg, orc):
         s.set_state(W, grad, alpha)
     Rg, gg, ag = g.residual(0)
     Ro, go, ao = o.residual(0)
-    assert np.abs(Rg - Ro).max() <= 1e-11 * np.abs(Ro).max()
+    err = np.abs(Rg - Ro).max()
+    print(f"residual: max |dR| / max |R| = {err / np.abs(Ro).max():.2e}, "
+          f"/ flux-sum scale = {err / o.flux_scale():.2e}", flush=True)
+    assert err <= 1e-12 * o.flux_scale()
     np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
     # alpha = prod 1/(1 + D^2) falls to ~1e-8 here (Mach-difference terms make D
     # large); its relative error is ~2 x the relative error of D, itself built
