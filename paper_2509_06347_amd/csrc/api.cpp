@@ -396,6 +396,7 @@ int upload(cgks_ctx* c) {
             std::sort(kids.begin(), kids.end());
             for (int k : kids) ch.push_back(k);
             coff[I + 1] = (int)ch.size();
+            D.maxchild = std::max(D.maxchild, coff[I + 1] - coff[I]);
         }
         TRY(dalloc(c, &D.V, m)); TRY(h2d(c, D.V, V));
         D.C = nullptr;

@@ -89,6 +89,7 @@ struct CoarseDev {
     double *Wb;                       /* second state buffer: LU-SGS iterations alternate W and Wb */
     int *parent;                      /* of the finer level's internal cells: this level's internal index */
     int *child_off, *child;           /* CSR of finer internal indices */
+    int maxchild = 0;                 /* most children of any cell */
     const int* pid;                   /* batched solves: problem id per cell (else null) */
     const double* ptab;
     const int* pact;                  /* per-problem "still cycling" flags (null: every cell cycles) */

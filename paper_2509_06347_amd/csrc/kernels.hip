@@ -1103,14 +1103,23 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams 
 }
 
 /* Restriction (Sec. 5.2): W0 = sum V W / V_c (FP64), Res* = sum Res (in T),
- * alpha = min. */
+ * alpha = min.  Eight lanes per coarse cell load its children, consecutive
+ * children in consecutive lanes (a coarse cell's children are contiguous in
+ * the finer level's order wherever the hierarchy is nested by index, so the
+ * loads coalesce), into LDS; the cell's first lane then sums them in child
+ * order, the order of a one-thread-per-cell loop.  nchunk = ceil(most
+ * children of any coarse cell / 8), the same for every block. */
+constexpr int RGRP = 8;
 template <int D, class T>
 __global__ void __launch_bounds__(CBLOCK) k_restrict(CoarseDev c, const double* Wf, const double* Vf,
-                                                   const double* resf, const double* af, int nfine) {
-    constexpr int NV = D + 2;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   const double* resf, const double* af, int nfine, int nchunk) {
+    constexpr int NV = D + 2, NQ = 2 * NV + 2, CPB = CBLOCK / RGRP;
+    __shared__ double buf[CPB][RGRP][NQ + 1];
+    const int lc = threadIdx.x / RGRP, j = threadIdx.x % RGRP;
+    const int I = blockIdx.x * CPB + lc;
     const int n = c.n;
-    if (I >= n || !active(c.pact, c.pid, I)) return;
+    const bool live = I < n && active(c.pact, c.pid, I);
+    const int k0 = live ? c.child_off[I] : 0, k1 = live ? c.child_off[I + 1] : 0;
     double w[NV], amin = 1.0e300;
     T r[NV];
 #pragma unroll
@@ -1118,16 +1127,36 @@ __global__ void __launch_bounds__(CBLOCK) k_restrict(CoarseDev c, const double* 
         w[q] = 0.0;
         r[q] = 0;
     }
-    for (int k = c.child_off[I]; k < c.child_off[I + 1]; ++k) {
-        const int i = c.child[k];
-        const double v = Vf[i];
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int k = k0 + ch * RGRP + j;
+        if (k < k1) {
+            const int i = c.child[k];
+            double* b = buf[lc][j];
+            b[0] = Vf[i];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            w[q] += v * Wf[q * nfine + i];
-            r[q] += (T)resf[q * nfine + i];
+            for (int q = 0; q < NV; ++q) {
+                b[1 + q] = Wf[q * nfine + i];
+                b[1 + NV + q] = resf[q * nfine + i];
+            }
+            b[1 + 2 * NV] = af[i];
         }
-        amin = fmin(amin, af[i]);
+        __syncthreads();
+        if (j == 0) {
+            const int m = min(RGRP, k1 - k0 - ch * RGRP);
+            for (int jj = 0; jj < m; ++jj) {
+                const double* b = buf[lc][jj];
+                const double v = b[0];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    w[q] += v * b[1 + q];
+                    r[q] += (T)b[1 + NV + q];
+                }
+                amin = fmin(amin, b[1 + 2 * NV]);
+            }
+        }
+        __syncthreads();
     }
+    if (j != 0 || !live) return;
     const double iv = 1.0 / c.V[I];
     T* Rs = reinterpret_cast<T*>(c.Rstar);
     T* dW = reinterpret_cast<T*>(c.dW);
@@ -1380,13 +1409,13 @@ void launch_restrict(cgks_ctx* c, int level, const double* Wfine) {
         Wf = F.W; Vf = F.V; rf = F.rhs; af = F.alpha; nfine = F.n;
     }
     const bool mx = c->p.precision == CGKS_MIXED;
-    const int nb = cblk(G.n);
+    const int nb = blocks(G.n, CBLOCK / RGRP), nch = (G.maxchild + RGRP - 1) / RGRP;
     if (c->dim == 2) {
-        if (mx) k_restrict<2, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
-        else k_restrict<2, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        if (mx) k_restrict<2, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine, nch);
+        else k_restrict<2, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine, nch);
     } else {
-        if (mx) k_restrict<3, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
-        else k_restrict<3, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine);
+        if (mx) k_restrict<3, float><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine, nch);
+        else k_restrict<3, double><<<nb, CBLOCK, 0, c->stream>>>(G, Wf, Vf, rf, af, nfine, nch);
     }
 }
 
