@@ -66,7 +66,7 @@ TRAFFIC_BYTES = {}
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of one launch (64 lanes per
 # wave instruction, FMA counted twice) divided by the launch's Gauss points.
 # Valid only for the flux source the counters were taken with.
-FLUX_FP64_OPS_PER_POINT = {("sphere_euler_mach6_3.1M", "k_flux<3>"): 7219}
+FLUX_FP64_OPS_PER_POINT = {}
 
 
 def workload(name):

@@ -216,45 +216,76 @@ struct RLds {
  * evaluates at its Gauss points.  Per cell and component the arithmetic, and
  * its order, is that of a one-thread-per-cell evaluation. */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
-template <int D>
-__global__ void __launch_bounds__(RTHREADS) k_recon(FineDev f, KParams kp0, int cells) {
+template <int D, int CELLS>
+__global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) k_recon(FineDev f, KParams kp0) {
     using S = Shape<D>;
     using L = RLds<D>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NCOL = S::NCOL, NK = S::NK;
+    constexpr int cells = CELLS, nt = CELLS * NS * NG, cs = CELLS + 1;   /* compile-time: index math by shifts */
+    static_assert(nt <= RTHREADS, "reconstruction block");
     extern __shared__ double lds[];
-    const int cs = cells + 1;
     int* nbf = reinterpret_cast<int*>(lds + (size_t)L::FIELDS * cs);   /* [NS][cells] neighbour, < 0 on boundaries */
     int* bad = nbf + NS * cells;
-    const int t = threadIdx.x, nt = blockDim.x;
+    const int t = threadIdx.x;
     const int n = f.n;
     const int i0 = blockIdx.x * cells;
 #define FLD(field, cl) lds[(field) * cs + (cl)]
 
-    /* ---- 1: loads, (cell, slot, component) ---- */
-    for (int u = t; u < cells * NS * NV; u += nt) {
-        const int cl = u % cells, r = u / cells, s = r % NS, q = r / NS;
-        const int i = i0 + cl;
-        if (i >= n || !active(f.pact, f.pid, i)) continue;
-        const int nb = f.slot_nbr[s * n + i];
-        double w = 0.0, g[D];
-        if (nb >= 0) {
-            w = f.W[q * n + nb];
+    /* ---- 1: loads, (cell, slot, component).  A thread takes at most
+     * ceil(NV / NG) = 2 items and issues all their loads before the first
+     * LDS store, so that the block waits on memory twice, not four times. ---- */
+    {
+        constexpr int NIT = (NV + NG - 1) / NG;
+        const int total = cells * NS * NV;
+        int cl[NIT], sl[NIT], qq[NIT], nb[NIT];
+        bool ok[NIT];
+        double w[NIT], g[NIT][D], own[NIT][3];
 #pragma unroll
-            for (int d = 0; d < D; ++d) g[d] = f.grad[(q * D + d) * n + nb];
+        for (int it = 0; it < NIT; ++it) {
+            const int u = t + it * nt;
+            cl[it] = u % cells;
+            const int r = u / cells, s = r % NS, q = r / NS, i = i0 + cl[it];
+            sl[it] = s;
+            qq[it] = q;
+            ok[it] = u < total && i < n && active(f.pact, f.pid, i);
+            nb[it] = -1;
+            own[it][0] = own[it][1] = own[it][2] = 0.0;
+            if (!ok[it]) continue;
+            nb[it] = f.slot_nbr[s * n + i];
+            if (s == 0) own[it][0] = f.W[q * n + i];
+            if (q == 0) own[it][1] = f.slot_S[s * n + i];
+            else if (q <= D) own[it][1] = f.slot_n[((q - 1) * NS + s) * n + i];
+            const int lin = s * NV + q;
+            if (lin < NQ) own[it][2] = f.mean0[lin * n + i];
+            else if (lin == NQ) own[it][2] = f.V[i];
+            else if (lin == NQ + 1) own[it][2] = f.h[i];
+            else if (lin == NQ + 2) own[it][2] = f.alpha[i];
         }
-        if (q == 0) nbf[s * cells + cl] = nb;
-        if (s == 0) FLD(L::W0 + q, cl) = f.W[q * n + i];
-        if (q == 0) FLD(L::GEO + s * (1 + D), cl) = f.slot_S[s * n + i];
-        else if (q <= D) FLD(L::GEO + s * (1 + D) + q, cl) = f.slot_n[((q - 1) * NS + s) * n + i];
-        const int lin = s * NV + q;
-        if (lin < NQ) FLD(L::MEAN + lin, cl) = f.mean0[lin * n + i];
-        else if (lin == NQ) FLD(L::CEL, cl) = f.V[i];
-        else if (lin == NQ + 1) FLD(L::CEL + 1, cl) = f.h[i];
-        else if (lin == NQ + 2) FLD(L::CEL + 2, cl) = f.alpha[i];
-        if (nb >= 0) {
-            FLD(L::WN + s * NV + q, cl) = w;
 #pragma unroll
-            for (int d = 0; d < D; ++d) FLD(L::GN + (s * NV + q) * D + d, cl) = g[d];
+        for (int it = 0; it < NIT; ++it) {
+            w[it] = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) g[it][d] = 0.0;
+            if (nb[it] < 0) continue;
+            const int q = qq[it], j = nb[it];
+            w[it] = f.W[q * n + j];
+#pragma unroll
+            for (int d = 0; d < D; ++d) g[it][d] = f.grad[(q * D + d) * n + j];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            if (!ok[it]) continue;
+            const int c = cl[it], s = sl[it], q = qq[it], lin = s * NV + q;
+            if (q == 0) nbf[s * cells + c] = nb[it];
+            if (s == 0) FLD(L::W0 + q, c) = own[it][0];
+            if (q <= D) FLD(L::GEO + s * (1 + D) + q, c) = own[it][1];
+            if (lin < NQ) FLD(L::MEAN + lin, c) = own[it][2];
+            else if (lin < NQ + 3) FLD(L::CEL + lin - NQ, c) = own[it][2];
+            if (nb[it] >= 0) {
+                FLD(L::WN + s * NV + q, c) = w[it];
+#pragma unroll
+                for (int d = 0; d < D; ++d) FLD(L::GN + (s * NV + q) * D + d, c) = g[it][d];
+            }
         }
     }
     for (int u = t; u < cells; u += nt) bad[u] = 0;
@@ -1249,8 +1280,13 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
     if (which == 0) {
         /* block = cells per block x faces x Gauss points */
         using S = Shape<D>;
-        const int cells = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
-        k_recon<D><<<blocks(f.n, cells), cells * S::NS * S::NG, RLds<D>::bytes(cells), st>>>(f, c->kp, cells);
+        const int want = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
+        const int cells = want <= 16 ? 16 : (want <= 32 || D == 3 ? 32 : 64);
+        const dim3 grid(blocks(f.n, cells)), blk(cells * S::NS * S::NG);
+        const size_t lds = RLds<D>::bytes(cells);
+        if (cells == 16) k_recon<D, 16><<<grid, blk, lds, st>>>(f, c->kp);
+        else if (cells == 32) k_recon<D, 32><<<grid, blk, lds, st>>>(f, c->kp);
+        else k_recon<D, (D == 2 ? 64 : 32)><<<grid, blk, lds, st>>>(f, c->kp);
     } else if (which == 1) {
         /* 64 / NG faces per wave */
         const int b = block ? block : c->blk_flux;

@@ -28,10 +28,11 @@ struct Mom {
 
 struct Prim {
     double rho, U[3], p, lam;
+    double T;    /* p / rho = 1 / (2 lam) */
 };
 
-__host__ __device__ __forceinline__ void full_table(double U, double lam, double* M, int n) {
-    const double h = 0.5 / lam;
+/* h = 1 / (2 lam) */
+__host__ __device__ __forceinline__ void full_table(double U, double h, double* M, int n) {
     M[0] = 1.0;
     M[1] = U;
 #pragma unroll
@@ -40,7 +41,7 @@ __host__ __device__ __forceinline__ void full_table(double U, double lam, double
 }
 
 /* Half-range u moments: sign > 0 integrates over u > 0, sign < 0 over u < 0. */
-__host__ __device__ __forceinline__ void half_table(double U, double lam, int sign, double* M) {
+__host__ __device__ __forceinline__ void half_table(double U, double lam, double h, int sign, double* M) {
     const double sl = sqrt(lam);
     const double ex = exp(-lam * U * U);
     const double c = 0.5 * ex / sqrt(M_PI * lam);
@@ -51,7 +52,6 @@ __host__ __device__ __forceinline__ void half_table(double U, double lam, int si
         M[0] = 0.5 * erfc(sl * U);
         M[1] = U * M[0] - c;
     }
-    const double h = 0.5 / lam;
 #pragma unroll
     for (int k = 2; k < 7; ++k) M[k] = U * M[k - 1] + (k - 1) * h * M[k - 2];
 }
@@ -59,14 +59,14 @@ __host__ __device__ __forceinline__ void half_table(double U, double lam, int si
 template <int D>
 __host__ __device__ __forceinline__ void make_mom(const KParams& kp, const Prim& P, int range, Mom<D>& M) {
     if (range == 0)
-        full_table(P.U[0], P.lam, M.u, 7);
+        full_table(P.U[0], P.T, M.u, 7);
     else
-        half_table(P.U[0], P.lam, range, M.u);
-    full_table(P.U[1], P.lam, M.v, 6);
-    if (D == 3) full_table(P.U[2], P.lam, M.w, 6);
+        half_table(P.U[0], P.lam, P.T, range, M.u);
+    full_table(P.U[1], P.T, M.v, 6);
+    if (D == 3) full_table(P.U[2], P.T, M.w, 6);
     M.x[0] = 1.0;
-    M.x[1] = kp.K / (2.0 * P.lam);
-    M.x[2] = kp.K * (kp.K + 2.0) / (4.0 * P.lam * P.lam);
+    M.x[1] = kp.K * P.T;
+    M.x[2] = kp.K * (kp.K + 2.0) * (P.T * P.T);
 }
 
 template <int D, int a, int b, int c, int k>
@@ -93,16 +93,40 @@ __host__ __device__ __forceinline__ void psi_mom(const Mom<D>& M, double* out) {
     }
 }
 
-/* <s(psi) u^a v^b w^c xi^(2k)> for s = s_0 + s_1 u + s_2 v [+ s_3 w] + s_E (|u|^2+xi^2)/2 */
-template <int D, int a, int b, int c, int k>
-__host__ __device__ __forceinline__ double smom(const double* s, const Mom<D>& M) {
-    double r = s[0] * mp<D, a, b, c, k>(M) + s[1] * mp<D, a + 1, b, c, k>(M) + s[2] * mp<D, a, b + 1, c, k>(M);
-    double e = mp<D, a + 2, b, c, k>(M) + mp<D, a, b + 2, c, k>(M) + mp<D, a, b, c, k + 1>(M);
+/* <s(psi) u^a v^b w^c xi^(2k)> for s = s_0 + s_1 u + s_2 v [+ s_3 w] + s_E (|u|^2+xi^2)/2,
+ * split by the factorisation of the Maxwellian moments into the part of s
+ * that varies with u (s_0 + s_1 u + s_E u^2 / 2, times <v^b w^c xi^2k>) and
+ * the rest (times <u^a>).  Each factor depends on fewer of (s, a, b, c, k)
+ * than the whole, so the many moments a flux needs share them. */
+template <int D, int a>
+__host__ __device__ __forceinline__ double s_upart(const double* s, const Mom<D>& M) {
+    return s[0] * M.u[a] + s[1] * M.u[a + 1] + 0.5 * s[D + 1] * M.u[a + 2];
+}
+
+template <int D, int b, int c, int k>
+__host__ __device__ __forceinline__ double tang(const Mom<D>& M) {
+    if constexpr (D == 3)
+        return M.v[b] * M.w[c] * M.x[k];
+    else
+        return M.v[b] * M.x[k];
+}
+
+template <int D, int b, int c, int k>
+__host__ __device__ __forceinline__ double s_tpart(const double* s, const Mom<D>& M) {
+    static_assert(b + 2 < 6 && c + 2 < 6 && k + 1 < 3, "moment order");
+    double r = s[2] * tang<D, b + 1, c, k>(M);
+    double e = tang<D, b + 2, c, k>(M) + tang<D, b, c, k + 1>(M);
     if constexpr (D == 3) {
-        r += s[3] * mp<D, a, b, c + 1, k>(M);
-        e += mp<D, a, b, c + 2, k>(M);
+        r += s[3] * tang<D, b, c + 1, k>(M);
+        e += tang<D, b, c + 2, k>(M);
     }
     return r + 0.5 * s[D + 1] * e;
+}
+
+template <int D, int a, int b, int c, int k>
+__host__ __device__ __forceinline__ double smom(const double* s, const Mom<D>& M) {
+    static_assert(a + 2 < 7, "moment order");
+    return s_upart<D, a>(s, M) * tang<D, b, c, k>(M) + M.u[a] * s_tpart<D, b, c, k>(s, M);
 }
 
 /* <s(psi) u^a v^b w^c psi_j> */
@@ -142,7 +166,7 @@ __host__ __device__ __forceinline__ void moment_inverse(const KParams& kp, const
     double u2 = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) u2 += P.U[j] * P.U[j];
-    const double B = u2 + N / (2.0 * P.lam);
+    const double B = u2 + N * P.T;
     double RE = 2.0 * b[D + 1] - B * b[0];
     double Rj[D];
     double UR = 0.0;
@@ -173,6 +197,7 @@ __host__ __device__ __forceinline__ void primitive(const KParams& kp, const doub
     }
     P.p = (kp.gamma - 1.0) * (W[D + 1] - 0.5 * ke);
     P.lam = W[0] / (2.0 * P.p);
+    P.T = P.p / W[0];
 }
 
 __host__ __device__ __forceinline__ double sutherland(const KParams& kp, double T) {
@@ -284,12 +309,12 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
     primitive<D>(kp, WR, PR);
 
     {   /* discontinuity feedback */
-        const double cl = sqrt(kp.gamma * PL.p / PL.rho), cr = sqrt(kp.gamma * PR.p / PR.rho);
+        const double icl = 1.0 / sqrt(kp.gamma * PL.p / PL.rho), icr = 1.0 / sqrt(kp.gamma * PR.p / PR.rho);
         const double dp = fabs(PL.p - PR.p);
         double Dv = dp / PL.p + dp / PR.p;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const double dm = PL.U[j] / cl - PR.U[j] / cr;
+            const double dm = PL.U[j] * icl - PR.U[j] * icr;
             Dv += dm * dm;
         }
         *alpha = 1.0 / (1.0 + Dv * Dv);
