@@ -385,7 +385,8 @@ def main():
 
     if args.warmup > 0:
         solver.run_cycles(args.warmup)
-    shapes = solver.autotune()        # launch shapes only; the arithmetic is unchanged
+    shapes = solver.autotune()        # launch shapes only; the per-cell arithmetic is unchanged
+    coarse_shapes = solver.coarse_shapes()
     solver.set_state(W0)              # restart the ramp: the timed cycles follow the warm-up
     if args.warmup > 0:
         solver.run_cycles(args.warmup)
@@ -439,6 +440,7 @@ def main():
            "config": {"workload": args.workload, "fine_cells": n_fine, "levels": 3,
                       "sizes": solver.sizes, **params},
            "roofline": roof, "fine_kernels": kern, "launch_shapes": shapes,
+           "coarse_cells_per_block": coarse_shapes,
            "chosen_form": chosen,
            "last_norm": float(hist[-1]) if len(hist) else None}
     del solver

@@ -250,10 +250,24 @@ int cgks_run_cycles(cgks_ctx* c, int n, double* history);
 int cgks_time_kernel(cgks_ctx* c, int kernel, int reps, double* avg_ms, int64_t* work_items);
 
 /* Choose the launch shape (threads per block) of each fine-residual kernel by
- * timing the candidates at the current state; invalidates captured graphs. */
+ * timing the candidates at the current state, and the cells per block (16,
+ * 32 or 64) of each coarse level's slot-parallel kernels by timing three
+ * LU-SGS iterations of the level per candidate.  The fine state is not
+ * modified; the coarse levels' states are (the next restriction overwrites
+ * them); the statistics counters are kept.  Invalidates captured graphs.
+ * The per-cell arithmetic does not depend on the shapes; the compiler may
+ * pair multiply-adds differently in differently sized kernels, so results
+ * agree to rounding, and bit for bit at equal shapes. */
 int cgks_autotune(cgks_ctx* c);
 /* Current launch shapes of the reconstruction, flux and gather kernels. */
 int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gather);
+/* Cells per block of the slot-parallel kernels of coarse levels 1..n (host
+ * int[n]; 0 for a level that runs the per-cell kernels or does not exist). */
+int cgks_coarse_shapes(cgks_ctx* c, int* cells_per_block, int n);
+/* Set them (host int[n], each 16, 32 or 64, else CGKS_EINVAL with nothing
+ * changed; entries beyond the context's coarse levels are ignored);
+ * invalidates captured graphs. */
+int cgks_set_coarse_shapes(cgks_ctx* c, const int* cells_per_block, int n);
 
 /* Batched solves: n independent problems (each a context with its own mesh,
  * Mach number, Reynolds number, wall temperature and angle of attack; all

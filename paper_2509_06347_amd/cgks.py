@@ -81,6 +81,8 @@ _sigs = {
     "cgks_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, _D, C.POINTER(C.c_int64)]),
     "cgks_autotune": (C.c_int, [_P]),
     "cgks_launch_shapes": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cgks_coarse_shapes": (C.c_int, [_P, C.POINTER(C.c_int), C.c_int]),
+    "cgks_set_coarse_shapes": (C.c_int, [_P, C.POINTER(C.c_int), C.c_int]),
     "cgks_batch_create": (C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P)]),
     "cgks_batch_autotune": (C.c_int, [_P]),
     "cgks_batch_run_cycles": (C.c_int, [_P, C.c_int, _D]),
@@ -313,6 +315,18 @@ class Solver:
         r, f, g = C.c_int(), C.c_int(), C.c_int()
         self._check(_lib.cgks_launch_shapes(self.ctx, C.byref(r), C.byref(f), C.byref(g)))
         return r.value, f.value, g.value
+
+    def coarse_shapes(self):
+        """Cells per block of each coarse level's slot-parallel kernels (0: per-cell kernels)."""
+        n = len(self.sizes) - 1
+        a = (C.c_int * max(n, 1))()
+        self._check(_lib.cgks_coarse_shapes(self.ctx, a, n))
+        return [a[i] for i in range(n)]
+
+    def set_coarse_shapes(self, cells_per_block):
+        v = list(cells_per_block)
+        a = (C.c_int * max(len(v), 1))(*v)
+        self._check(_lib.cgks_set_coarse_shapes(self.ctx, a, len(v)))
 
     def stats(self):
         a, b = C.c_int64(), C.c_int64()

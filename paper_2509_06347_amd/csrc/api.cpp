@@ -847,6 +847,12 @@ int cgks_stats(cgks_ctx* c, int64_t* guard_hits, int64_t* prolong_skips) {
 
 extern "C" int cgks_autotune(cgks_ctx* c) {
     TRY(check_level(c, 0));
+    /* statistics counters, restored at the end: the timed launches below may
+     * advance them (positivity guard, update safeguard) */
+    unsigned long long guard = 0, skips = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&guard, c->fine.guard, sizeof(guard), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&skips, c->ws.skips, sizeof(skips), hipMemcpyDeviceToHost));
     /* launch shape of each fine kernel: the fastest candidate at the current state */
     static const int cand[3][3] = {{16, 32, 64}, {64, 128, 256}, {64, 128, 256}};  /* recon: cells per block */
     int best[3] = {c->blk_recon, c->blk_flux, c->blk_gather};
@@ -871,11 +877,37 @@ extern "C" int cgks_autotune(cgks_ctx* c) {
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     c->blk_recon = best[0];
     c->blk_flux = best[1];
     c->blk_gather = best[2];
+    /* cells per block of each coarse level's slot-parallel kernels: the fastest
+     * over three LU-SGS iterations at the level's current state (the coarse
+     * states are overwritten by the next restriction) */
+    for (size_t l = 1; l < c->hl.size(); ++l) {
+        CoarseDev& L = c->coarse[l - 1];
+        if (!coarse_slot_parallel(L)) continue;
+        float tbest = 1e30f;
+        int sbest = L.sc;
+        for (int sc : {16, 32, 64}) {
+            L.sc = sc;
+            launch_lusgs_iters(c, (int)l, 1);
+            HIPCHK(hipEventRecord(e0, c->stream));
+            launch_lusgs_iters(c, (int)l, 3);
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < tbest) {
+                tbest = ms;
+                sbest = sc;
+            }
+        }
+        L.sc = sbest;
+    }
+    HIPCHK(hipMemcpy(c->fine.guard, &guard, sizeof(guard), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->ws.skips, &skips, sizeof(skips), hipMemcpyHostToDevice));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     invalidate_graph(c);
     return CGKS_OK;
 }
@@ -885,6 +917,24 @@ extern "C" int cgks_launch_shapes(cgks_ctx* c, int* recon, int* flux, int* gathe
     if (recon) *recon = c->blk_recon;
     if (flux) *flux = c->blk_flux;
     if (gather) *gather = c->blk_gather;
+    return CGKS_OK;
+}
+
+extern "C" int cgks_set_coarse_shapes(cgks_ctx* c, const int* cells_per_block, int n) {
+    if (!c || n < 0 || (n > 0 && !cells_per_block)) return CGKS_EINVAL;
+    for (int l = 0; l < n; ++l) {
+        const int v = cells_per_block[l];
+        if (v != 16 && v != 32 && v != 64) return fail(c, CGKS_EINVAL, "cells per block must be 16, 32 or 64");
+    }
+    for (int l = 0; l < n && l < (int)c->coarse.size(); ++l) c->coarse[l].sc = cells_per_block[l];
+    invalidate_graph(c);
+    return CGKS_OK;
+}
+
+extern "C" int cgks_coarse_shapes(cgks_ctx* c, int* cells_per_block, int n) {
+    if (!c || n < 0 || (n > 0 && !cells_per_block)) return CGKS_EINVAL;
+    for (int l = 0; l < n; ++l)
+        cells_per_block[l] = l < (int)c->coarse.size() && coarse_slot_parallel(c->coarse[l]) ? c->coarse[l].sc : 0;
     return CGKS_OK;
 }
 

@@ -90,6 +90,7 @@ struct CoarseDev {
     int *parent;                      /* of the finer level's internal cells: this level's internal index */
     int *child_off, *child;           /* CSR of finer internal indices */
     int maxchild = 0;                 /* most children of any cell */
+    int sc = 64;                      /* cells per block of the slot-parallel kernels (16, 32, 64) */
     const int* pid;                   /* batched solves: problem id per cell (else null) */
     const double* ptab;
     const int* pact;                  /* per-problem "still cycling" flags (null: every cell cycles) */
@@ -174,6 +175,8 @@ void launch_save_state(cgks_ctx* c);
 void launch_coarse_update(cgks_ctx* c, int level);
 /* n LU-SGS iterations on a coarse level (right-hand side, sweeps, update) */
 void launch_lusgs_iters(cgks_ctx* c, int level, int n);
+/* whether a coarse level runs the slot-parallel kernels (whose block size the autotuner picks) */
+bool coarse_slot_parallel(const CoarseDev& L);
 
 /* modes of launch_fine_residual */
 enum { FINE_EVAL = 0, FINE_STEP = 1, FINE_STEP_NORM = 2, FINE_RESTRICT = 3 };

@@ -21,6 +21,8 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cgks_internal.h"
 #include "kinetic.hpp"
 
@@ -510,7 +512,7 @@ __device__ __forceinline__ void eval_poly(const double* __restrict__ rec, const 
  * t = dt in Gauss-point order and multiplies their DF factors, and writes
  * the face's record [sum wS F, sum wS W(dt), DF product]. */
 constexpr int FTHREADS = 256;
-template <int D>
+template <int D, bool STATE>
 __global__ void __launch_bounds__(FTHREADS) k_flux(FineDev f, KParams kp0) {
     using S = Shape<D>;
     constexpr int NV = S::NV, NG = S::NG, NPR = S::NPR, FO = S::FO, NS = S::NS;
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(FTHREADS) k_flux(FineDev f, KParams kp0) {
         double dt = f.dt[L];
         if (R >= 0) dt = fmin(dt, f.dt[R]);
         double Fk[NV], Gk[NV];
-        gks_flux<D>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
+        gks_flux<D, STATE>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
         const double ws = f.fS[fc] / NG;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
@@ -856,15 +858,17 @@ __global__ void __launch_bounds__(CBLOCK) k_coarse_rhs(CoarseDev c, KParams kp0,
  * Same arithmetic as one thread per cell, with nslot times the parallelism
  * (the coarse levels are too small to fill the chip one cell per thread). */
 constexpr int MAXS = 8;     /* most face slots handled by the slot-parallel kernels */
-constexpr int SCELLS = 64;  /* cells per block of the slot-parallel kernels */
-template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KParams kp0, int mode, int hi1,
-                                                                double* Wout1) {
+/* Cells per block of the slot-parallel kernels (SC) is a template parameter,
+ * chosen per coarse level by the autotuner among 16, 32 and 64: small levels
+ * and colour ranges spread over more compute units with smaller blocks. */
+template <int D, class T, int SC>
+__global__ void __launch_bounds__(SC * MAXS) k_coarse_rhs_s(CoarseDev c, KParams kp0, int mode, int hi1,
+                                                            double* Wout1) {
     constexpr int NV = D + 2;
     constexpr int NX = NV + 3;                 /* S F[q], S r, S (|u.n| + c), S^2 */
-    __shared__ double part[NX][MAXS][SCELLS];
+    __shared__ double part[NX][MAXS][SC];
     const int tx = threadIdx.x, s = threadIdx.y;
-    const int I = blockIdx.x * SCELLS + tx;
+    const int I = blockIdx.x * SC + tx;
     const int n = c.n;
     const bool live = I < n && active(c.pact, c.pid, I);
     const KParams kp = localize(kp0, c.ptab, c.pid, live ? I : 0);
@@ -974,9 +978,9 @@ __global__ void __launch_bounds__(SCELLS * MAXS) k_coarse_rhs_s(CoarseDev c, KPa
 
 /* One colour of an LU-SGS sweep with one thread per (cell, face slot); the
  * slot-0 thread combines the neighbour terms in slot order and updates dW. */
-template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
-                                                           double* Wout);
+template <int D, class T, int SC>
+__global__ void __launch_bounds__(SC * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
+                                                       double* Wout);
 
 /* Increment of the normal Euler flux T(W + dW) - T(W).  In FP64 it is the
  * literal difference; in FP32 it is written in terms of the increments so no
@@ -1067,13 +1071,13 @@ __global__ void __launch_bounds__(CBLOCK) k_lusgs(CoarseDev c, KParams kp, int l
     }
 }
 
-template <int D, class T>
-__global__ void __launch_bounds__(SCELLS * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
-                                                           double* Wout) {
+template <int D, class T, int SC>
+__global__ void __launch_bounds__(SC * MAXS) k_lusgs_s(CoarseDev c, KParams kp, int lo, int hi, int fwd,
+                                                       double* Wout) {
     constexpr int NV = D + 2;
-    __shared__ T part[NV][MAXS][SCELLS];
+    __shared__ T part[NV][MAXS][SC];
     const int tx = threadIdx.x, s = threadIdx.y;
-    const int I = lo + blockIdx.x * SCELLS + tx;
+    const int I = lo + blockIdx.x * SC + tx;
     const int n = c.n;
     const bool live = I < hi && active(c.pact, c.pid, I);
     T* dW = reinterpret_cast<T*>(c.dW);
@@ -1268,6 +1272,15 @@ __global__ void __launch_bounds__(BLOCK) k_save_if_ok(const double* a0, double* 
 
 /* ------------------------------------------------------------- launchers --- */
 
+/* Calls f with std::integral_constant<int, SC> for the slot-parallel block
+ * size sc (16, 32 or 64; anything else takes 64). */
+template <class F>
+static void with_sc(int sc, F&& f) {
+    if (sc == 16) f(std::integral_constant<int, 16>{});
+    else if (sc == 32) f(std::integral_constant<int, 32>{});
+    else f(std::integral_constant<int, 64>{});
+}
+
 static inline int nblk(long m) { return (int)((m + BLOCK - 1) / BLOCK); }
 static inline int cblk(long m) { return (int)((m + CBLOCK - 1) / CBLOCK); }
 
@@ -1291,7 +1304,11 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
         /* 64 / NG faces per wave */
         const int b = block ? block : c->blk_flux;
         const long waves = ((long)f.nf + 64 / Shape<D>::NG - 1) / (64 / Shape<D>::NG);
-        k_flux<D><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        /* the residual for restriction uses no slopes (the state at t = dt);
+         * inviscid, its flux needs none of their moments */
+        const bool lite = (mode & ~FINE_KEEP) == FINE_RESTRICT && !(c->kp.reynolds > 0.0) && !f.pid;
+        if (lite) k_flux<D, false><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        else k_flux<D, true><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
     } else {
         /* the norm partials use a fixed 256-thread block */
         const int m = mode & ~FINE_KEEP;
@@ -1338,8 +1355,11 @@ template <int D, class T>
 static void coarse_rhs(cgks_ctx* c, CoarseDev& L, int mode) {
     const int hi1 = mode == COARSE_RHS && L.ncolor > 0 ? L.color_off[1] : 0;
     if (L.nslot <= MAXS) {
-        const dim3 blk(SCELLS, L.nslot);
-        k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), blk, 0, c->stream>>>(L, c->kp, mode, hi1, nullptr);
+        with_sc(L.sc, [&](auto scv) {
+            constexpr int SC = decltype(scv)::value;
+            k_coarse_rhs_s<D, T, SC><<<blocks(L.n, SC), dim3(SC, L.nslot), 0, c->stream>>>(L, c->kp, mode, hi1,
+                                                                                       nullptr);
+        });
     } else {
         k_coarse_rhs<D, T><<<cblk(L.n), CBLOCK, 0, c->stream>>>(L, c->kp, mode, hi1);
     }
@@ -1362,8 +1382,11 @@ static void lusgs(cgks_ctx* c, CoarseDev& L) {
             const int lo = L.color_off[col], hi = L.color_off[col + 1];
             if (hi <= lo) continue;
             if (L.nslot <= MAXS)
-                k_lusgs_s<D, T><<<blocks(hi - lo, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
-                                                                                                   pass == 0, nullptr);
+                with_sc(L.sc, [&](auto scv) {
+                    constexpr int SC = decltype(scv)::value;
+                    k_lusgs_s<D, T, SC><<<blocks(hi - lo, SC), dim3(SC, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
+                                                                                               pass == 0, nullptr);
+                });
             else
                 k_lusgs<D, T><<<cblk(hi - lo), CBLOCK, 0, c->stream>>>(L, c->kp, lo, hi, pass == 0);
         }
@@ -1384,18 +1407,26 @@ template <int D, class T>
 static void lusgs_iter_pingpong(cgks_ctx* c, const CoarseDev& L, double* Wout) {
     const int C = L.ncolor;
     const int hi1 = C > 0 ? L.color_off[1] : 0;
-    k_coarse_rhs_s<D, T><<<blocks(L.n, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, COARSE_RHS, hi1,
-                                                                                      C == 1 ? Wout : nullptr);
+    with_sc(L.sc, [&](auto scv) {
+        constexpr int SC = decltype(scv)::value;
+        k_coarse_rhs_s<D, T, SC><<<blocks(L.n, SC), dim3(SC, L.nslot), 0, c->stream>>>(L, c->kp, COARSE_RHS, hi1,
+                                                                                   C == 1 ? Wout : nullptr);
+    });
     for (int pass = 0; pass < 2; ++pass)
         for (int k = 1; k < C; ++k) {
             const int col = pass == 0 ? k : C - 1 - k;
             const int lo = L.color_off[col], hi = L.color_off[col + 1];
             if (hi <= lo) continue;
             double* w = (pass == 1 || col == C - 1) ? Wout : nullptr;
-            k_lusgs_s<D, T><<<blocks(hi - lo, SCELLS), dim3(SCELLS, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
-                                                                                               pass == 0, w);
+            with_sc(L.sc, [&](auto scv) {
+                constexpr int SC = decltype(scv)::value;
+                k_lusgs_s<D, T, SC><<<blocks(hi - lo, SC), dim3(SC, L.nslot), 0, c->stream>>>(L, c->kp, lo, hi,
+                                                                                           pass == 0, w);
+            });
         }
 }
+
+bool coarse_slot_parallel(const CoarseDev& L) { return L.nslot <= MAXS && L.ncolor >= 1; }
 
 void launch_lusgs_iters(cgks_ctx* c, int level, int n) {
     CoarseDev& L = c->coarse[level - 1];

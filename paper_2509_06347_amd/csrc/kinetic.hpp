@@ -291,10 +291,13 @@ __host__ __device__ __forceinline__ void rot_grad(const double (*e)[3], const do
  * In:  W and Cartesian gradients of the left/right reconstructed states, the
  *      unit normal n (left -> right), the flux time dt.
  * Out: F  time-averaged flux over [0, dt] (Cartesian, not area-scaled),
- *      G  conservative variables carried by f at t = dt (Sec. 2.4),
+ *      G  conservative variables carried by f at t = dt (Sec. 2.4); with
+ *         STATE false (an inviscid residual whose slopes are not used) its
+ *         moments, and those of the time-averaged f that only the heat-flux
+ *         correction needs, are skipped and G is zero,
  *      alpha  DF factor of this point (Sec. 3.3).
  */
-template <int D>
+template <int D, bool STATE = true>
 __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const double (*gLc)[D], const double* WRc,
                          const double (*gRc)[D], const double* n, double dt, double* F, double* G,
                          double* alpha) {
@@ -403,14 +406,16 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
 #pragma unroll
         for (int q = 0; q < NV; ++q) Fl[q] -= P.rho * q6 * t[q];
         /* state at t = dt and conserved moments of the time-averaged f */
-        psi_mom<D, 0, 0, 0>(half, t);
-        sdot_mom<D, 0>(s, half, t2);
-        double tA[NV];
-        spsi_mom<D, 0, 0, 0>(A, half, tA);
+        if constexpr (STATE) {
+            psi_mom<D, 0, 0, 0>(half, t);
+            sdot_mom<D, 0>(s, half, t2);
+            double tA[NV];
+            spsi_mom<D, 0, 0, 0>(A, half, tA);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            Gl[q] += P.rho * (ex * t[q] - (dt + tau) * ex * t2[q] - tau * ex * tA[q]);
-            Wf[q] += P.rho * (q4 * t[q] - q5 * t2[q] - q6 * tA[q]);
+            for (int q = 0; q < NV; ++q) {
+                Gl[q] += P.rho * (ex * t[q] - (dt + tau) * ex * t2[q] - tau * ex * tA[q]);
+                Wf[q] += P.rho * (q4 * t[q] - q5 * t2[q] - q6 * tA[q]);
+            }
         }
     }
 
@@ -437,19 +442,21 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
         spsi_mom<D, 1, 0, 0>(A, full, tAu);
 #pragma unroll
         for (int q = 0; q < NV; ++q) Fl[q] += PC.rho * (q1 * tu[q] + q2 * tau2[q] + q3 * tAu[q]);
-        double tp[NV], tA[NV];
-        psi_mom<D, 0, 0, 0>(full, tp);
-        spsi_mom<D, 0, 0, 0>(A, full, tA);
+        if constexpr (STATE) {
+            double tp[NV], tA[NV];
+            psi_mom<D, 0, 0, 0>(full, tp);
+            spsi_mom<D, 0, 0, 0>(A, full, tA);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            Gl[q] += PC.rho * (C1 * tp[q] + C2 * t2[q] + C3 * tA[q]);
-            Wf[q] += PC.rho * (q1 * tp[q] + q2 * t2[q] + q3 * tA[q]);
+            for (int q = 0; q < NV; ++q) {
+                Gl[q] += PC.rho * (C1 * tp[q] + C2 * t2[q] + C3 * tA[q]);
+                Wf[q] += PC.rho * (q1 * tp[q] + q2 * t2[q] + q3 * tA[q]);
+            }
         }
     }
     const double idt = 1.0 / dt;
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q] *= idt;
-    if (kp.reynolds > 0.0) {
+    if (STATE && kp.reynolds > 0.0) {
         /* BGK heat flux 1/2 <(u-U)(|u-U|^2+xi^2) f> from flux and conserved moments */
         double u2 = 0.0, UF = 0.0, UW = 0.0;
 #pragma unroll

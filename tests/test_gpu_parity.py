@@ -434,3 +434,46 @@ def test_batch_solve_freezes_converged_members(cg):
         Wb, gb, ab = members[b].get_state()
         Ws, gs, as_ = singles[b].get_state()
         assert np.array_equal(Wb, Ws) and np.array_equal(gb, gs) and np.array_equal(ab, as_), b
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_block_sizes_and_autotune_keep_the_arithmetic(cg, dim):
+    """The coarse levels' slot-parallel kernels at 16, 32 and 64 cells per block,
+    and the autotuner's choice, run the same per-cell arithmetic: V-cycles agree
+    to rounding (the compiler may pair the multiply-adds of the differently
+    sized instantiations differently), which the impulsive Mach 6 start
+    amplifies over seven cycles to ~1e-12 of the state, inside the oracle
+    trajectory bar (1e-10).  Equal shapes agree bit for bit.  The autotuner
+    keeps the fine state and the statistics counters."""
+    if dim == 2:
+        mesh, prm = sm.annulus(32, 8, jitter=0.1, seed=1, nref=2, wall_tag=sm.ISOTHERMAL), dict(mach=3.0, reynolds=1e3)
+    else:
+        mesh, prm = sm.sphere_shell_kuhn(8, 4, 4, nref=2), dict(mach=6.0, cfl_ramp=10)
+    runs = []
+    for shape in ([64, 64], [64, 64], [16, 16], [32, 16], "auto"):
+        s = cg.Solver(mesh, n_levels=3, **prm)
+        s.init_freestream()
+        h0 = s.run_cycles(3)
+        if shape == "auto":
+            W0, g0, a0 = s.get_state()
+            st0 = s.stats()
+            s.autotune()
+            W1, g1, a1 = s.get_state()
+            assert np.array_equal(W0, W1) and np.array_equal(g0, g1) and np.array_equal(a0, a1)
+            assert s.stats() == st0
+            assert all(v in (16, 32, 64) for v in s.coarse_shapes())
+            shape = s.coarse_shapes()
+        else:
+            s.set_coarse_shapes(shape)
+            assert s.coarse_shapes() == shape
+        h = np.concatenate([h0, s.run_cycles(4)])
+        runs.append((shape, h, s.get_state()[0]))
+    # the same shapes: bit for bit
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    for shape, h, W in runs[2:]:
+        dh = np.abs(h - runs[0][1]).max() / np.abs(runs[0][1]).max()
+        dW = np.abs(W - runs[0][2]).max() / np.abs(runs[0][2]).max()
+        print(f"[case] dim {dim} coarse cells per block {shape}: norms {dh:.1e}, state {dW:.1e}", flush=True)
+        assert dh <= 1e-12 and dW <= 1e-10
+    with pytest.raises(cg.CgksError):
+        s.set_coarse_shapes([48, 64])

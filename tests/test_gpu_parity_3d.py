@@ -2,8 +2,10 @@
 
 Meshes: a jittered box of 2^3 hexahedra split into 6 tetrahedra each, refined
 1 -> 8 twice (3,072 / 384 / 48 cells), far field on five sides and a wall on
-z = 0 (slip for Euler, isothermal for Navier-Stokes); free stream at 10 degrees
-in the x-y plane, parallel to the wall.  Bars as in the 2-D parity tests.
+z = 0 (slip for Euler, isothermal or adiabatic no-slip for Navier-Stokes);
+free stream at 10 degrees in the x-y plane, parallel to the wall.  Bars as in
+the 2-D parity tests.  Also: the Mach 6 sphere shells, and viscous flow past
+the Kuhn sphere with an adiabatic wall.
 """
 import numpy as np
 import pytest
@@ -27,6 +29,8 @@ CASES = {
                   dict(dim=3, mach=0.5, aoa_deg=10.0)),
     "ns_box": (lambda: sm.box_tets(2, nref=2, jitter=0.1, seed=4, tags={"z0": sm.ISOTHERMAL}),
                dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
+    "ns_box_adiabatic": (lambda: sm.box_tets(2, nref=2, jitter=0.1, seed=6, tags={"z0": sm.ADIABATIC}),
+                         dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
 }
 
 
@@ -174,3 +178,38 @@ def test_sphere_vcycle_trajectory_parity(cg, orc):
     Wo, _, _ = o.get_state()
     assert np.abs(Wg - Wo).max() <= 1e-9 * np.abs(Wo).max()
     assert g.stats()[1] == o.stats()[1]
+
+
+def test_kuhn_sphere_ns_adiabatic_wall_parity(cg, orc):
+    """Navier-Stokes (Re 100, Mach 0.5) past the Kuhn sphere shell with an
+    adiabatic no-slip wall (23,040 tetrahedra): fine residual, slopes, DF and
+    time steps at a perturbed state, then two V-cycles."""
+    mesh = sm.sphere_shell_kuhn(8, 4, 2, nref=2, wall_tag=sm.ADIABATIC)
+    params = dict(dim=3, mach=0.5, reynolds=100.0)
+    g, o = _pair(cg, orc, mesh, **params)
+    W, grad, alpha = _sphere_state(o, 0.5, seed=13)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    err = np.abs(Rg - Ro).max() / np.abs(Ro).max()
+    print(f"residual: max |dR| / max |R| = {err:.2e}", flush=True)
+    assert err <= 1e-12
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    # DF: a product over the cell's 12 Gauss points of 1 / (1 + D^2), D built
+    # from jumps of reconstructed pressures and Mach numbers that cancel near
+    # the wall; one near-wall cell of 23,040 differs by 1.5e-12
+    np.testing.assert_allclose(ag, ao, rtol=1e-11, atol=1e-13)
+    dg, ig = g.time_steps(0)
+    do, io = o.time_steps(0)
+    np.testing.assert_allclose(dg, do, rtol=1e-13)
+    for s in (g, o):
+        s.set_state(W, None, None)
+    ng = g.run_cycles(2)
+    no = np.array([o.vcycle() for _ in range(2)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    werr = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    print(f"two V-cycles: state err {werr:.2e}", flush=True)
+    assert werr <= 1e-10
