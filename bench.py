@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Mcell·V-cycles/s and time-to-1e-10 residual, plain FP64 vs chosen form"
 MI355X_HBM_GBS = 8000.0
 MI355X_FP64_VECTOR_TFLOPS = 78.6
+MI355X_BF16_MFMA_TFLOPS = 2500.0   # dense
 
 # Algorithmic HBM bytes per fine cell of one reconstruction launch: every input
 # it needs, read once (the neighbours' states are other cells' own states), and
@@ -283,6 +284,50 @@ def ablations(cgks, max_cycles, hyper_cycles):
                             "variants": hyper}}
 
 
+# ------------------------------------------------------------- warm-start net --
+
+MLP_LAYERS = ((5, 256), (256, 256), (256, 256), (256, 4))
+
+
+def mlp_bench(cgks, steps, batch):
+    """The warm-start network's BF16-MFMA training step and forward pass on a
+    synthetic batch (inputs and targets drawn once, resident on the device).
+    Algorithmic FLOPs use the layers' real sizes (the kernels pad the 5-wide
+    input and the 4-wide output to the MFMA tile): 2 per multiply-add,
+    forward once and backward twice (input and weight gradients)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(5)
+    X = torch.randn(batch, 5, device="cuda", dtype=torch.float32, generator=g)
+    Y = torch.randn(batch, 4, device="cuda", dtype=torch.float32, generator=g)
+    out = torch.empty(batch, 4, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    net = cgks.MLP(seed=0)
+    macs = sum(i * o for i, o in MLP_LAYERS)
+    for _ in range(5):
+        net.train_step(X, Y, 1e-3)
+        net.forward(X, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(X, Y, 1e-3)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(X, out)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    peak = MI355X_BF16_MFMA_TFLOPS
+    tr = 6.0 * macs * batch / t_train / 1e12
+    fw = 2.0 * macs * batch / t_fwd / 1e12
+    net.close()
+    return {"batch": batch, "layers": [list(l) for l in MLP_LAYERS], "steps": steps,
+            "train_step_ms": t_train * 1e3, "train_tflops": tr,
+            "forward_ms": t_fwd * 1e3, "forward_tflops": fw,
+            "peak_bf16_tflops": peak, "train_frac": tr / peak, "forward_frac": fw / peak,
+            "timing": "host clock over the calls; each training step reads its loss back"}
+
+
 # --------------------------------------------------------------- CPU oracle --
 
 def cpu_model():
@@ -361,6 +406,10 @@ def main():
     ap.add_argument("--ablations", action="store_true",
                     help="print the smoother/relaxation ablation table (one JSON line) instead")
     ap.add_argument("--hyper-cycles", type=int, default=3000)
+    ap.add_argument("--mlp", action="store_true",
+                    help="print the warm-start network's training and inference rates (one JSON line) instead")
+    ap.add_argument("--mlp-steps", type=int, default=200)
+    ap.add_argument("--mlp-batch", type=int, default=16384)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -375,6 +424,9 @@ def main():
     torch.cuda.set_device(0)
     if args.ablations:
         print(json.dumps({"ablations": ablations(cgks, args.max_cycles, args.hyper_cycles)}), flush=True)
+        return
+    if args.mlp:
+        print(json.dumps({"mlp": mlp_bench(cgks, args.mlp_steps, args.mlp_batch)}), flush=True)
         return
     print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
     mesh, params = workload(args.workload)
