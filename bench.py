@@ -61,13 +61,19 @@ RECON_BYTES_PER_CELL = {
 # FETCH_SIZE and WRITE_SIZE counter runs of this script, each scaled by the
 # counter's reading for a plain device copy of known size.  Valid only for the
 # kernel source the counters were taken with; absent (null) otherwise.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {
+    # FETCH_SIZE 3,933,000 KiB x 2.0 + WRITE_SIZE 1,983,700 KiB x 1.0, median per launch
+    ("sphere_euler_mach6_3.1M", "k_recon<3, 16>"): (3.9330e6 * 2.0 + 1.9837e6 * 1.0) * 1024,
+}
 
 # FP64 operations the flux kernel executes per face Gauss point, from the
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of one launch (64 lanes per
 # wave instruction, FMA counted twice) divided by the launch's Gauss points.
 # Valid only for the flux source the counters were taken with.
-FLUX_FP64_OPS_PER_POINT = {}
+FLUX_FP64_OPS_PER_POINT = {
+    # 64 x (ADD 8.7139e7 + MUL 2.2698e8 + 2 FMA 5.9897e8 + TRANS 1.3662e7) / 18,627,840 points
+    ("sphere_euler_mach6_3.1M", "k_flux<3, true>"): 5242,
+}
 
 
 def workload(name):
@@ -458,12 +464,13 @@ def main():
     rb = RECON_BYTES_PER_CELL[d]
     rec = kern["recon"]
     gbs = rb * rec["work_items"] / (rec["avg_ms"] / 1e3) / 1e9
-    roof = {"bound": "hbm", "kernel": f"k_recon<{d}>", "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, f"k_recon<{d}>")),
+    rname = f"k_recon<{d}, {shapes[0]}>"     # the autotuned cells per block
+    roof = {"bound": "hbm", "kernel": rname, "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, rname)),
             "avg_ms": rec["avg_ms"], "work_items": rec["work_items"], "bytes_per_item": rb}
     # the flux kernel against the FP64 vector peak, from its counted operations
     fx = kern["flux"]
-    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}>"))
+    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}, true>"))
     if ops:
         tf = ops * fx["work_items"] / (fx["avg_ms"] / 1e3) / 1e12
         kern["flux"]["fp64"] = {"bound": "fp64", "achieved": tf, "peak": MI355X_FP64_VECTOR_TFLOPS,
