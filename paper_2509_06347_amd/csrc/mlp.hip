@@ -10,7 +10,9 @@
  *
  * GEMM: C[M x N] = A[M x K] B[K x N] with arbitrary strides, one 64 x 64 block
  * tile per 256-thread block (four wave64s, each 32 x 32 = 2 x 2 MFMA tiles of
- * v_mfma_f32_16x16x32_bf16), K staged through LDS in steps of 32.
+ * v_mfma_f32_16x16x32_bf16), K staged through LDS in steps of 32; operands
+ * with a unit stride along k or along their rows are loaded 16 bytes per
+ * thread (the training step's GEMMs all are).
  * Fragment layout of the 16x16x32 BF16 MFMA: lane l holds A row (l % 16) and
  * B column (l % 16), each with the 8 consecutive K values 8 * (l / 16) ..;
  * the accumulator holds column (l % 16), rows 4 * (l / 16) .. + 3.
@@ -18,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <random>
@@ -55,13 +58,54 @@ __device__ __forceinline__ float dsilu_f(float z) {
  * and, for EPI_STORE, writes to Cz + z zstride (split-K partials).
  * Out-of-range A/B elements read as zero; only in-range C elements are stored.
  */
-template <int EPI>
+/* Operand layouts for the tile loader: X(r, k) = X[r * srow + k * sk]. */
+enum { LAY_ANY = 0, LAY_K = 1, LAY_R = 2 };   /* any strides; k contiguous; r contiguous */
+
+/* Stage a 64 x 32 (rows x k) tile of X into Xs[r][k] (zeros outside [0, R) x
+ * [k0, ke)).  LAY_K: each thread loads 8 consecutive k of one row (16 bytes);
+ * LAY_R: 8 consecutive rows of one k (16 bytes), transposed into LDS; both
+ * need 16-byte aligned rows / columns, which the host checks.  LAY_ANY: one
+ * element at a time. */
+template <int LAY>
+__device__ __forceinline__ void load_tile(__bf16 (*Xs)[40], const __bf16* __restrict__ X, long srow, long sk, int r0,
+                                          int R, int k0, int ke, int t) {
+    if constexpr (LAY == LAY_K) {
+        const int r = t >> 2, kc = (t & 3) * 8, gr = r0 + r, gk = k0 + kc;
+        if (gr < R && gk + 8 <= ke) {
+            *reinterpret_cast<uint4*>(&Xs[r][kc]) = *reinterpret_cast<const uint4*>(X + (long)gr * srow + gk);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                Xs[r][kc + e] = (gr < R && gk + e < ke) ? X[(long)gr * srow + gk + e] : (__bf16)0.0f;
+        }
+    } else if constexpr (LAY == LAY_R) {
+        const int kk = t >> 3, rc = (t & 7) * 8, gr = r0 + rc, gk = k0 + kk;
+        bf16x8 v;
+        if (gk < ke && gr + 8 <= R) {
+            v = *reinterpret_cast<const bf16x8*>(X + gr + (long)gk * sk);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (gk < ke && gr + e < R) ? X[gr + e + (long)gk * sk] : (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Xs[rc + e][kk] = v[e];
+    } else {
+        const int r = t >> 2, kc = (t & 3) * 8, gr = r0 + r;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kc + e;
+            Xs[r][kc + e] = (gr < R && k < ke) ? X[(long)gr * srow + (long)k * sk] : (__bf16)0.0f;
+        }
+    }
+}
+
+template <int EPI, int LA, int LB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const __bf16* __restrict__ A, long sam, long sak,
                                               const __bf16* __restrict__ B, long sbk, long sbn, float* Cz, long ldc,
                                               __bf16* Cb, long ldb, const float* bias, const float* Zin, long ldz,
                                               int kc, long zstride) {
-    __shared__ __bf16 As[64][40];   /* [m][k], padded rows */
-    __shared__ __bf16 Bs[64][40];   /* [n][k] */
+    __shared__ __attribute__((aligned(16))) __bf16 As[64][40];   /* [m][k], padded rows (80 bytes) */
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[64][40];   /* [n][k] */
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -70,16 +114,11 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const __bf16*
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = t >> 2, lk = (t & 3) * 8;   /* loader: row/col lr, k chunk lk..lk+7 */
     const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
     if (EPI == EPI_STORE) Cz += blockIdx.z * zstride;
     for (int k0 = kb; k0 < ke; k0 += 32) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int m = m0 + lr, k = k0 + lk + e, n = n0 + lr;
-            As[lr][lk + e] = (m < M && k < ke) ? A[(long)m * sam + (long)k * sak] : (__bf16)0.0f;
-            Bs[lr][lk + e] = (n < N && k < ke) ? B[(long)k * sbk + (long)n * sbn] : (__bf16)0.0f;
-        }
+        load_tile<LA>(As, A, sam, sak, m0, M, k0, ke, t);
+        load_tile<LB>(Bs, B, sbn, sbk, n0, N, k0, ke, t);
         __syncthreads();
         const int fr = lane & 15, fk = (lane >> 4) * 8;
 #pragma unroll
@@ -158,11 +197,30 @@ __global__ void k_out_grad(const float* out, const float* Y, __bf16* G, float* s
 }
 
 /* Column sums of a [n][ncol] bf16 matrix in a fixed order (bias gradients). */
-__global__ void k_colsum(const __bf16* G, int n, int ncol, float* out) {
+/* Column sums of G [n][ld] (bf16), columns 0..ncol-1, in two fixed-order
+ * passes: block b sums rows [b R, (b + 1) R) of every column (consecutive
+ * threads read consecutive columns of a row; the row loads are unrolled so
+ * they are in flight together), then one block per column reduces the block
+ * partials in a fixed tree. */
+constexpr int CS_ROWS = 64;
+__global__ void k_colsum_part(const __bf16* G, int n, int ld, int ncol, float* part) {
+    const int c = threadIdx.x, b = blockIdx.x;
+    if (c >= ncol) return;
+    const int i0 = b * CS_ROWS;
+    float v = 0.0f;
+#pragma unroll 16
+    for (int r = 0; r < CS_ROWS; ++r) {
+        const int i = i0 + r;
+        v += i < n ? (float)G[(long)i * ld + c] : 0.0f;
+    }
+    part[(long)b * ncol + c] = v;
+}
+
+__global__ void k_colsum_final(const float* part, int nb, int ncol, float* out) {
     const int c = blockIdx.x;
     __shared__ float sh[256];
     float v = 0.0f;
-    for (int i = threadIdx.x; i < n; i += 256) v += (float)G[(long)i * ncol + c];
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[(long)b * ncol + c];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -172,7 +230,21 @@ __global__ void k_colsum(const __bf16* G, int n, int ncol, float* out) {
     if (threadIdx.x == 0) out[c] = sh[0];
 }
 
-__global__ void k_sum(const float* a, int n, float* out) {
+/* Mean of a[0..n): 256-element blocks reduced in a fixed tree order, then the
+ * block sums added in block order by one block. */
+__global__ void k_sum_part(const float* a, int n, float* part) {
+    __shared__ float sh[256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    sh[threadIdx.x] = i < n ? a[i] : 0.0f;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum(const float* a, int n, float* out, int count) {
     __shared__ float sh[256];
     float v = 0.0f;
     for (int i = threadIdx.x; i < n; i += 256) v += a[i];
@@ -182,7 +254,7 @@ __global__ void k_sum(const float* a, int n, float* out) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0] / (float)n;
+    if (threadIdx.x == 0) *out = sh[0] / (float)count;
 }
 
 /* Adam on fp32 master parameters; refreshes the bf16 weight copy (bias: wb null). */
@@ -313,13 +385,14 @@ struct cgks_mlp {
     __bf16* Wb[NL];             /* bf16 copy of W, [DOUT][KPAD] */
     int t = 0;
     int cap = 0;                /* samples the workspace holds */
+    size_t part_cnt = 0;        /* floats in part */
     __bf16* H[NL];              /* layer inputs (bf16), [cap][KPAD] */
     float* Z[NL];               /* pre-activations (fp32), [cap][NPAD] */
     float* out;                 /* [cap][16] */
     __bf16* G[NL + 1];          /* gradients w.r.t. layer outputs, bf16 */
     float* se;                  /* per-sample squared error */
     float* dloss;
-    float* part;                /* split-K partials, SPLITK * 256 * 256 */
+    float* part;                /* split-K partials (SPLITK * 256 * 256) and bias-gradient block sums */
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
     std::string err;
@@ -349,16 +422,66 @@ int ensure_ws(cgks_mlp* m, int n) {
     ok &= mal(m, &m->out, (size_t)cap * 16) == hipSuccess;
     for (int l = 0; l <= NL; ++l) ok &= mal(m, &m->G[l], (size_t)cap * (l < NL ? KPAD[l] : 16)) == hipSuccess;
     ok &= mal(m, &m->se, (size_t)cap) == hipSuccess;
+    /* the partial buffer also holds the bias-gradient block sums, n / 64 x 256 */
+    const size_t need = ((size_t)cap / CS_ROWS + 1) * 256;
+    if (ok && need > m->part_cnt) {
+        ok &= mal(m, &m->part, need) == hipSuccess;
+        if (ok) m->part_cnt = need;
+    }
     if (!ok) return CGKS_EDEVICE;
     m->cap = cap;
     return CGKS_OK;
+}
+
+/* Loader layout of an operand X(r, k) = X[r * srow + k * sk]: 16-byte vector
+ * loads need a unit stride along k (or r) and 16-byte aligned rows (columns). */
+int layout(const __bf16* X, long srow, long sk) {
+    const bool al = reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    if (al && sk == 1 && srow % 8 == 0) return LAY_K;
+    if (al && srow == 1 && sk % 8 == 0) return LAY_R;
+    return LAY_ANY;
+}
+
+template <int EPI, int LA, int LB>
+void launch_gemm(hipStream_t st, dim3 grid, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B,
+                 long sbk, long sbn, float* Cz, long ldc, __bf16* Cb, long ldb, const float* bias, const float* Zin,
+                 long ldz, int kc, long zs) {
+    k_gemm<EPI, LA, LB><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc,
+                                              zs);
+}
+
+template <int EPI, int LA>
+void dispatch_b(int lb, hipStream_t st, dim3 grid, int M, int N, int K, const __bf16* A, long sam, long sak,
+                const __bf16* B, long sbk, long sbn, float* Cz, long ldc, __bf16* Cb, long ldb, const float* bias,
+                const float* Zin, long ldz, int kc, long zs) {
+    if (lb == LAY_K)
+        launch_gemm<EPI, LA, LAY_K>(st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc, zs);
+    else if (lb == LAY_R)
+        launch_gemm<EPI, LA, LAY_R>(st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc, zs);
+    else
+        launch_gemm<EPI, LA, LAY_ANY>(st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc,
+                                      zs);
+}
+
+template <int EPI>
+void gemm_any(hipStream_t st, dim3 grid, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B,
+              long sbk, long sbn, float* Cz, long ldc, __bf16* Cb, long ldb, const float* bias, const float* Zin,
+              long ldz, int kc, long zs) {
+    const int la = layout(A, sam, sak), lb = layout(B, sbn, sbk);
+    if (la == LAY_K)
+        dispatch_b<EPI, LAY_K>(lb, st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc, zs);
+    else if (la == LAY_R)
+        dispatch_b<EPI, LAY_R>(lb, st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc, zs);
+    else
+        dispatch_b<EPI, LAY_ANY>(lb, st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, kc,
+                                 zs);
 }
 
 template <int EPI>
 void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B, long sbk, long sbn,
           float* Cz, long ldc, __bf16* Cb, long ldb, const float* bias, const float* Zin, long ldz) {
     dim3 grid(nb(N, 64), nb(M, 64), 1);
-    k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, K, 0);
+    gemm_any<EPI>(st, grid, M, N, K, A, sam, sak, B, sbk, sbn, Cz, ldc, Cb, ldb, bias, Zin, ldz, K, 0);
 }
 
 /* C[M][N] (ldc == N) = A B with the K range split over up to SPLITK blocks;
@@ -369,13 +492,13 @@ void gemm_splitk(cgks_mlp* m, int M, int N, int K, const __bf16* A, long sam, lo
 
 void gemm_splitk(cgks_mlp* m, int M, int N, int K, const __bf16* A, long sam, long sak, const __bf16* B, long sbk,
                  long sbn, float* C) {
-    const int nz = std::max(1, std::min(SPLITK, K / 1024));
+    const int nz = std::max(1, std::min(SPLITK, K / 256));   /* >= 8 k-steps of 32 per block */
     const int kc = ((K + nz - 1) / nz + 31) / 32 * 32;
     const int z = (K + kc - 1) / kc;
     dim3 grid(nb(N, 64), nb(M, 64), z);
     const long cnt = (long)M * N;
-    k_gemm<EPI_STORE><<<grid, 256, 0, m->stream>>>(M, N, K, A, sam, sak, B, sbk, sbn, m->part, N, nullptr, 0, nullptr,
-                                                    nullptr, 0, kc, cnt);
+    gemm_any<EPI_STORE>(m->stream, grid, M, N, K, A, sam, sak, B, sbk, sbn, m->part, N, nullptr, 0, nullptr, nullptr, 0,
+                        kc, cnt);
     k_splitk_reduce<<<nb(cnt, 256), 256, 0, m->stream>>>(m->part, z, cnt, C);
 }
 
@@ -398,12 +521,22 @@ void forward(cgks_mlp* m, const float* X, int n) {
 void backward(cgks_mlp* m, const float* Y, int n) {
     hipStream_t st = m->stream;
     k_out_grad<<<nb(n, 256), 256, 0, st>>>(m->out, Y, m->G[NL], m->se, n);
-    k_sum<<<1, 256, 0, st>>>(m->se, n, m->dloss);
+    const int nbs = nb(n, 256);
+    k_sum_part<<<nbs, 256, 0, st>>>(m->se, n, m->part);
+    k_sum<<<1, 256, 0, st>>>(m->part, nbs, m->dloss, n);
     for (int l = NL - 1; l >= 0; --l) {
         const int ldg = (l == NL - 1) ? 16 : KPAD[l + 1];  /* row stride of the output gradient */
         /* dW[o][k] = sum_i G[i][o] H[i][k] : A(o, i) = G[i][o], B(i, k) = H[i][k] */
         gemm_splitk(m, DOUT[l], KPAD[l], n, m->G[l + 1], 1, ldg, m->H[l], KPAD[l], 1, m->Gr[l][0]);
-        k_colsum<<<DOUT[l], 256, 0, st>>>(m->G[l + 1], n, ldg, m->Gr[l][1]);
+        {
+            /* bias gradient: column sums of the output gradient, through the
+             * split-K partial buffer (free again once the reduce above ran;
+             * n / 64 blocks x 256 columns fit it for every n the workspace
+             * holds) */
+            const int nch = nb(n, CS_ROWS);
+            k_colsum_part<<<nch, 256, 0, st>>>(m->G[l + 1], n, ldg, DOUT[l], m->part);
+            k_colsum_final<<<DOUT[l], 256, 0, st>>>(m->part, nch, DOUT[l], m->Gr[l][1]);
+        }
         if (l > 0) {
             /* G_l[i][k] = (sum_o G[i][o] W[o][k]) * silu'(Z_{l-1}[i][k]) */
             gemm<EPI_DSILU>(st, n, DIN[l], DOUT[l], m->G[l + 1], ldg, 1, m->Wb[l], KPAD[l], 1, nullptr, 0, m->G[l],
@@ -421,6 +554,7 @@ int cgks_mlp_create(cgks_mlp** out, int seed) {
     cgks_mlp* m = new cgks_mlp();
     std::mt19937_64 rng((uint64_t)seed);
     bool ok = mal(m, &m->dloss, 1) == hipSuccess && mal(m, &m->part, (size_t)SPLITK * 256 * 256) == hipSuccess;
+    m->part_cnt = (size_t)SPLITK * 256 * 256;
     for (int l = 0; l < NL && ok; ++l) {
         const size_t nw = wcount(l), nbias = DOUT[l];
         std::vector<float> W(nw, 0.0f), b(nbias, 0.0f);
