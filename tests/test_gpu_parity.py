@@ -203,6 +203,12 @@ AGG_CASES = {
                            dict(mach=0.7, aoa_deg=12.0)),
     "3d_box_slip": (lambda: sm.box_tets(2, nref=2, jitter=0.1, seed=2, tags={"z0": sm.SLIP}),
                     dict(dim=3, mach=0.5, aoa_deg=10.0)),
+    # meshes generated directly at the fine size (no refinement, so no nesting
+    # at all): the whole hierarchy comes from Alg. 3
+    "2d_unrefined_slip": (lambda: sm.annulus(48, 16, jitter=0.25, seed=7, nref=0, wall_tag=sm.SLIP),
+                          dict(mach=0.4)),
+    "3d_unrefined_ns_adiabatic": (lambda: sm.box_tets(5, nref=0, jitter=0.2, seed=9, tags={"z0": sm.ADIABATIC}),
+                                  dict(dim=3, mach=0.5, reynolds=100.0)),
 }
 
 
