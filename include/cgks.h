@@ -123,6 +123,12 @@ typedef struct cgks_params {
                                   20 % less work per cycle, but on the steady Re 40 cylinder it stalls
                                   near 5e-5 where the paper's cycle reaches 1e-10.  Default 0: the
                                   paper's cycle */
+    int slip_wall_p1;          /* 1: cells with a face on a slip wall use the alpha-scaled Green-Gauss
+                                  p^1 alone (nonlinear weights 0 and 1; not in the paper).  The compact
+                                  p^2 of a slip-wall triangle is fitted to two neighbours beside it
+                                  along the wall and makes the explicit fine step grow there; with
+                                  this and tau_c1 = 0.1 the inviscid slip-wall cylinder converges to
+                                  round-off.  Default 0 */
 } cgks_params;
 
 /* Mesh input (host memory, copied by cgks_mesh_setup; the caller keeps ownership).

@@ -51,6 +51,8 @@ typedef struct orc_params {
     int cfl_ramp;              /* implicit-CFL start-up ramp length in V-cycles; 0 = none */
     double relax_beta;         /* fixed relaxation weight used when df_relax = 2 or 3 */
     int shared_residual;       /* 1: restrict the last fine step's input state and residual */
+    int slip_wall_p1;          /* 1: cells with a slip-wall face use the Green-Gauss p^1 alone
+                                  (weights 0 and 1; an option, not the paper's reconstruction) */
 } orc_params;
 
 typedef struct orc_mesh {

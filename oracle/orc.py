@@ -29,7 +29,7 @@ class Params(C.Structure):
         ("weno_gamma_large", C.c_double), ("weno_eps", C.c_double),
         ("lusgs_omega", C.c_double), ("skew_limit", C.c_double),
         ("slope_relax", C.c_double), ("update_limit", C.c_double), ("cfl_ramp", C.c_int),
-        ("relax_beta", C.c_double), ("shared_residual", C.c_int),
+        ("relax_beta", C.c_double), ("shared_residual", C.c_int), ("slip_wall_p1", C.c_int),
     ]
 
 
@@ -39,7 +39,7 @@ DEFAULTS = dict(dim=2, gamma=1.4, prandtl=0.72, mach=0.38, aoa_deg=0.0, reynolds
                 n_levels=3, n_pre_fine=1, n_post=0, n_sweeps=6, df_relax=1, df_prolong=1,
                 precision=0, tau_c1=0.01, tau_c2=1.0, weno_gamma_large=0.95,
                 weno_eps=1e-14, lusgs_omega=1.0, skew_limit=0.2, slope_relax=0.3,
-                update_limit=0.5, cfl_ramp=0, relax_beta=0.5, shared_residual=0)
+                update_limit=0.5, cfl_ramp=0, relax_beta=0.5, shared_residual=0, slip_wall_p1=0)
 
 
 class OrcMesh(C.Structure):

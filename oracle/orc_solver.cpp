@@ -199,6 +199,15 @@ void build_rec(orc_ctx* c, int i, CellRec& r) {
         double w0 = gl * (1.0 + t0 * t0), w1 = gs * (1.0 + t1 * t1);
         r.w0[q] = w0 / (w0 + w1);
         r.w1[q] = w1 / (w0 + w1);
+        if (c->p.slip_wall_p1) {
+            /* option (not the paper's): a cell on a slip wall keeps the
+             * Green-Gauss sub-stencil alone */
+            for (int fi : L0.cf[i])
+                if (L0.faces[fi].R < 0 && L0.faces[fi].tag == TAG_SLIP) {
+                    r.w0[q] = 0.0;
+                    r.w1[q] = 1.0;
+                }
+        }
     }
     /* Positivity guard at every Gauss point of the cell. */
     for (int fi : L0.cf[i]) {

@@ -38,7 +38,7 @@ class Params(C.Structure):
         ("weno_gamma_large", C.c_double), ("weno_eps", C.c_double),
         ("lusgs_omega", C.c_double), ("skew_limit", C.c_double),
         ("slope_relax", C.c_double), ("update_limit", C.c_double), ("cfl_ramp", C.c_int),
-        ("relax_beta", C.c_double), ("shared_residual", C.c_int),
+        ("relax_beta", C.c_double), ("shared_residual", C.c_int), ("slip_wall_p1", C.c_int),
     ]
 
 

@@ -91,6 +91,7 @@ void make_kparams(cgks_ctx* c) {
     k.relax_beta = p.relax_beta;
     k.df_relax = p.df_relax;
     k.df_prolong = p.df_prolong;
+    k.slip_wall_p1 = p.slip_wall_p1;
     const double a = p.aoa_deg * M_PI / 180.0;
     k.u_inf[0] = p.mach * std::cos(a);
     k.u_inf[1] = p.mach * std::sin(a);
@@ -466,6 +467,7 @@ void cgks_default_params(cgks_params* p) {
     p->cfl_ramp = 0;
     p->relax_beta = 0.5;
     p->shared_residual = 0;
+    p->slip_wall_p1 = 0;
 }
 
 const char* cgks_strerror(int code) {
@@ -496,6 +498,7 @@ int cgks_create(const cgks_params* p, cgks_ctx** out) {
     if (p->df_relax < 0 || p->df_relax > 3) return CGKS_EINVAL;
     if (!(p->relax_beta >= 0.0 && p->relax_beta <= 1.0)) return CGKS_EINVAL;
     if (p->shared_residual != 0 && p->shared_residual != 1) return CGKS_EINVAL;
+    if (p->slip_wall_p1 != 0 && p->slip_wall_p1 != 1) return CGKS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CGKS_EDEVICE;
     cgks_ctx* c = new cgks_ctx();
@@ -959,6 +962,7 @@ bool same_shared_params(const cgks_params& a, const cgks_params& b) {
            a.lusgs_omega == b.lusgs_omega && a.slope_relax == b.slope_relax &&
            a.update_limit == b.update_limit && a.cfl_ramp == b.cfl_ramp && a.relax_beta == b.relax_beta &&
            a.shared_residual == b.shared_residual &&
+           a.slip_wall_p1 == b.slip_wall_p1 &&
            ((a.reynolds > 0.0) == (b.reynolds > 0.0));
 }
 

@@ -121,6 +121,7 @@ struct KParams {
     double gamma, K, prandtl, mach, reynolds, mu_inf, Tinf, S_suth, Tw;
     double cfl_exp, cfl_imp, tau_c1, tau_c2, g_large, g_small, eps, omega, slope_relax, update_limit;
     int df_relax, df_prolong;
+    int slip_wall_p1;                 /* slip-wall cells use p^1 alone */
     int cfl_ramp;                     /* 0: fixed implicit CFL */
     double relax_beta;                /* fixed relaxation weight (df_relax = 2) */
     const int* ncyc;                  /* device: V-cycles begun since the state was set */

@@ -190,9 +190,10 @@ struct RLds {
     static constexpr int CEL = GEO + NS * (1 + D);   /* volume, h, DF factor */
     static constexpr int COEF = CEL + 3;             /* [NV][NK] p^2 part, Green-Gauss part */
     static constexpr int FIELDS = COEF + NV * NK;
-    /* bytes for `cells` cells: the fields, then per-cell neighbour flags [NS] and the guard flag */
+    /* bytes for `cells` cells: the fields, then per-cell neighbours [NS], the
+     * guard flag and the slip-wall flag */
     static constexpr size_t bytes(int cells) {
-        return (size_t)FIELDS * (cells + 1) * sizeof(double) + (size_t)(NS + 1) * cells * sizeof(int);
+        return (size_t)FIELDS * (cells + 1) * sizeof(double) + (size_t)(NS + 2) * cells * sizeof(int);
     }
 };
 
@@ -228,6 +229,7 @@ __global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) k_recon(Fi
     extern __shared__ double lds[];
     int* nbf = reinterpret_cast<int*>(lds + (size_t)L::FIELDS * cs);   /* [NS][cells] neighbour, < 0 on boundaries */
     int* bad = nbf + NS * cells;
+    int* slip = bad + cells;   /* the cell has a slip-wall face */
     const int t = threadIdx.x;
     const int n = f.n;
     const int i0 = blockIdx.x * cells;
@@ -290,7 +292,7 @@ __global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) k_recon(Fi
             }
         }
     }
-    for (int u = t; u < cells; u += nt) bad[u] = 0;
+    for (int u = t; u < cells; u += nt) bad[u] = slip[u] = 0;
     __syncthreads();
 
     /* ---- 2: ghost averages of boundary faces, (cell, slot); operator rows,
@@ -305,7 +307,9 @@ __global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) k_recon(Fi
         for (int q = 0; q < NV; ++q) W0[q] = FLD(L::W0 + q, cl);
 #pragma unroll
         for (int d = 0; d < D; ++d) nout[d] = FLD(L::GEO + s * (1 + D) + 1 + d, cl);
-        ghost_state<D, false>(kp, f.slot_tag[s * n + i], W0, nullptr, nout, Wg, nullptr);
+        const int tag = f.slot_tag[s * n + i];
+        if (tag == CGKS_TAG_SLIP) slip[cl] = 1;
+        ghost_state<D, false>(kp, tag, W0, nullptr, nout, Wg, nullptr);
 #pragma unroll
         for (int q = 0; q < NV; ++q) FLD(L::WN + s * NV + q, cl) = Wg[q];
     }
@@ -402,7 +406,11 @@ __global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) k_recon(Fi
         const double tz = fabs(b0 - b1);
         const double t0 = tz / (b0 + kp.eps), t1 = tz / (b1 + kp.eps);
         const double w0 = kp.g_large * (1.0 + t0 * t0), w1 = kp.g_small * (1.0 + t1 * t1);
-        const double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
+        double o0 = w0 / (w0 + w1), o1 = w1 / (w0 + w1);
+        if (kp.slip_wall_p1 && slip[cl]) {   /* slip-wall cells: p^1 alone (option, not the paper's) */
+            o0 = 0.0;
+            o1 = 1.0;
+        }
         const double cp2 = o0 / kp.g_large, cp1 = o1 - o0 * kp.g_small / kp.g_large;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) FLD(L::COEF + q * NK + k, cl) = cp2 * a[k];

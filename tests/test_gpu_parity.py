@@ -483,3 +483,30 @@ def test_coarse_block_sizes_and_autotune_keep_the_arithmetic(cg, dim):
         assert dh <= 1e-12 and dW <= 1e-10
     with pytest.raises(cg.CgksError):
         s.set_coarse_shapes([48, 64])
+
+
+def test_slip_wall_p1_option_parity(cg, orc):
+    """The slip-wall p^1 option with tau_c1 = 0.1 (the pair with which the
+    inviscid slip-wall cylinder converges): residual at a perturbed state and
+    a 5-cycle trajectory from the free stream, against the oracle."""
+    mesh = sm.annulus(32, 8, jitter=0.15, seed=0, nref=1, wall_tag=sm.SLIP)
+    params = dict(mach=0.38, tau_c1=0.1, slip_wall_p1=1)
+    g, o = _pair(cg, orc, mesh, **params)
+    W, grad, alpha = _perturbed(mesh, o, 0.38, seed=21)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    err = np.abs(Rg - Ro).max() / np.abs(Ro).max()
+    print(f"residual: max |dR| / max |R| = {err:.2e}", flush=True)
+    assert err <= 1e-12
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    np.testing.assert_allclose(ag, ao, rtol=1e-12, atol=1e-13)
+    for s in (g, o):
+        s.init_freestream()
+    ng = g.run_cycles(5)
+    no = np.array([o.vcycle() for _ in range(5)])
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, _, _ = g.get_state()
+    Wo, _, _ = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()

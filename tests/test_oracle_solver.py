@@ -494,3 +494,48 @@ def test_multicolour_lusgs_equals_sequential_lusgs_3d(orc):
         (o.smooth_sequential if seq else o.smooth)(1, 2)
         runs.append(o.get_level_state(1)[0])
     assert np.array_equal(runs[0], runs[1])
+
+
+def _cells_touching(mesh, tag):
+    """Indices of the cells with a boundary face of the given tag, and of their
+    face neighbours (cells sharing dim nodes with one of them)."""
+    nodes = set()
+    faces = [tuple(sorted(f)) for f, t in zip(mesh.bfaces, mesh.btags) if t == tag]
+    cells = [tuple(sorted(c)) for c in mesh.cells]
+    wall = {i for i, c in enumerate(cells) for f in faces if set(f) <= set(c)}
+    near = set(wall)
+    wall_sets = [set(cells[i]) for i in wall]
+    for i, c in enumerate(cells):
+        if any(len(set(c) & w) == mesh.dim for w in wall_sets):
+            near.add(i)
+    return wall, near
+
+
+def test_slip_wall_p1_option_acts_on_slip_wall_cells_only(orc):
+    """The slip_wall_p1 option (not the paper's reconstruction) replaces the
+    combined polynomial of slip-wall cells by p^1: without slip walls it
+    changes nothing bit for bit; with them it changes the residual of the
+    slip-wall cells and of their face neighbours (whose faces see those
+    polynomials) and of no other cell."""
+    ff = sm.annulus(12, 4, jitter=0.15, seed=3, nref=1, wall_tag=sm.FARFIELD)
+    wall = sm.annulus(12, 4, jitter=0.15, seed=3, nref=1, wall_tag=sm.SLIP)
+    res = []
+    for opt in (0, 1):
+        o = orc.Oracle(ff, n_levels=1, mach=0.4, slip_wall_p1=opt)
+        V, C = o.cell_geometry(0)
+        o.set_state(smooth_state(C, mach=0.4), None, None)
+        res.append(o.residual(0))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    o0 = orc.Oracle(wall, n_levels=1, mach=0.4)
+    o1 = orc.Oracle(wall, n_levels=1, mach=0.4, slip_wall_p1=1)
+    V, C = o0.cell_geometry(0)
+    W = smooth_state(C, mach=0.4)
+    for o in (o0, o1):
+        o.set_state(W, None, None)
+    R0, _, _ = o0.residual(0)
+    R1, _, _ = o1.residual(0)
+    wall_cells, near = _cells_touching(wall, sm.SLIP)
+    changed = set(np.nonzero(np.any(R0 != R1, axis=1))[0].tolist())
+    assert changed and changed <= near
+    assert wall_cells <= changed
