@@ -94,6 +94,9 @@ int orc_set_level_state(orc_ctx* c, int level, const double* W, const double* W0
 int orc_get_level_state(orc_ctx* c, int level, double* W, double* W0, double* F, double* alpha);
 
 int orc_residual(orc_ctx* c, int level, double* R, double* gradW_new, double* alpha_out);
+/* The fine residual, evolved slopes and DF of the m listed cells only (original order
+ * indices), equal to orc_residual's values for those cells; [m][nvar], [m][nvar][dim], [m]. */
+int orc_residual_cells(orc_ctx* c, const int* cells, int m, double* R, double* gradW_new, double* alpha_out);
 int orc_time_steps(orc_ctx* c, int level, double* dt_exp, double* dt_imp);
 int orc_smooth(orc_ctx* c, int level, int n);
 int orc_smooth_sequential(orc_ctx* c, int level, int n);

@@ -219,6 +219,17 @@ class Oracle:
         self._chk(lib().orc_residual(self.ctx, level, _dp(R), _dp(g), _dp(a)))
         return R, g, a
 
+    def residual_cells(self, cells):
+        """Fine residual, evolved slopes and DF of the listed cells only (the
+        same values as residual(0) for those rows)."""
+        idx = np.ascontiguousarray(cells, dtype=np.int32)
+        m = len(idx)
+        R = np.zeros((m, self.nvar))
+        g = np.zeros((m, self.nvar, self.dim))
+        a = np.zeros(m)
+        self._chk(lib().orc_residual_cells(self.ctx, _ip(idx), m, _dp(R), _dp(g), _dp(a)))
+        return R, g, a
+
     def time_steps(self, level=0):
         n = self.sizes[level][0]
         de, di = np.zeros(n), np.zeros(n)

@@ -262,6 +262,59 @@ void time_steps(orc_ctx* c, int l, const std::vector<double>& W, std::vector<dou
     }
 }
 
+/* One fine face (Secs. 2.3-2.4): the S-scaled, Gauss-weighted flux, the
+ * Gauss-weighted conserved variables at t = dt and the product of the Gauss
+ * points' DF factors, from the reconstructions of its cells (rr is null on a
+ * boundary face, whose right state is the ghost). */
+static void face_sums(orc_ctx* c, const Face& f, const CellRec& rl, const CellRec* rr, double dt, double* Fs,
+                      double* Gs, double* as) {
+    const int nv = c->nvar;
+    for (int q = 0; q < nv; ++q) Fs[q] = Gs[q] = 0.0;
+    *as = 1.0;
+    for (int k = 0; k < f.ngp; ++k) {
+        double Wl[5], gl[15], Wr[5], gr[15], F[5], G[5], a;
+        eval_state(c, f.L, rl, f.gp[k], Wl, gl);
+        if (rr)
+            eval_state(c, f.R, *rr, f.gp[k], Wr, gr);
+        else
+            ghost(c->p, f.tag, Wl, gl, f.n, Wr, gr);
+        gks_point(c->p, Wl, gl, Wr, gr, f.n, dt, F, G, &a);
+        for (int q = 0; q < nv; ++q) {
+            Fs[q] += f.w[k] * F[q];
+            Gs[q] += f.w[k] * G[q];
+        }
+        *as *= a;
+    }
+    for (int q = 0; q < nv; ++q) Fs[q] *= f.S;
+}
+
+/* Cell i's residual, evolved slopes and DF from its faces' sums, taken in the
+ * cell's local face order (Fl, Gl, al indexed by position in cf[i]). */
+static void gather_cell(const orc_ctx* c, int i, const double* Fl, const double* Gl, const double* al, double* R,
+                        double* g, double* a) {
+    const int dim = c->dim, nv = c->nvar;
+    const Level& L0 = c->lv[0];
+    const std::vector<int>& cf = L0.cf[i];
+    for (int q = 0; q < nv; ++q) R[q] = 0.0;
+    for (int k = 0; k < nv * dim; ++k) g[k] = 0.0;
+    *a = 1.0;
+    for (size_t t = 0; t < cf.size(); ++t) {
+        const Face& f = L0.faces[cf[t]];
+        double sg = (f.L == i) ? 1.0 : -1.0;
+        for (int q = 0; q < nv; ++q) R[q] += sg * Fl[t * nv + q];
+        *a *= al[t];
+    }
+    for (size_t t = 0; t < cf.size(); ++t) {
+        const Face& f = L0.faces[cf[t]];
+        double n[3];
+        outward(f, i, dim, n);
+        for (int q = 0; q < nv; ++q)
+            for (int d = 0; d < dim; ++d) g[q * dim + d] += f.S * Gl[t * nv + q] * n[d];
+    }
+    for (int q = 0; q < nv; ++q)
+        for (int d = 0; d < dim; ++d) g[q * dim + d] *= *a / L0.V[i];
+}
+
 /* Fine-level residual (Secs. 2.2-2.4, 3): R, new slopes and DF. */
 void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew,
                    std::vector<double>& anew, std::vector<double>& dte) {
@@ -279,21 +332,8 @@ void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew
         const Face& f = L0.faces[fi];
         double dt = dte[f.L];
         if (f.R >= 0) dt = std::min(dt, dte[f.R]);
-        for (int k = 0; k < f.ngp; ++k) {
-            double Wl[5], gl[15], Wr[5], gr[15], F[5], G[5], a;
-            eval_state(c, f.L, rec[f.L], f.gp[k], Wl, gl);
-            if (f.R >= 0)
-                eval_state(c, f.R, rec[f.R], f.gp[k], Wr, gr);
-            else
-                ghost(c->p, f.tag, Wl, gl, f.n, Wr, gr);
-            gks_point(c->p, Wl, gl, Wr, gr, f.n, dt, F, G, &a);
-            for (int q = 0; q < nv; ++q) {
-                Ff[fi * nv + q] += f.w[k] * F[q];
-                Gf[fi * nv + q] += f.w[k] * G[q];
-            }
-            af[fi] *= a;
-        }
-        for (int q = 0; q < nv; ++q) Ff[fi * nv + q] *= f.S;
+        face_sums(c, f, rec[f.L], f.R >= 0 ? &rec[f.R] : nullptr, dt, &Ff[(size_t)fi * nv], &Gf[(size_t)fi * nv],
+                  &af[fi]);
     }
     c->face_flux = Ff;
     R.assign((size_t)L0.n * nv, 0.0);
@@ -301,21 +341,60 @@ void fine_residual(orc_ctx* c, std::vector<double>& R, std::vector<double>& gnew
     anew.assign(L0.n, 1.0);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < L0.n; ++i) {
+        const std::vector<int>& cf = L0.cf[i];
+        std::vector<double> Fl(cf.size() * nv), Gl(cf.size() * nv), al(cf.size());
+        for (size_t t = 0; t < cf.size(); ++t) {
+            for (int q = 0; q < nv; ++q) {
+                Fl[t * nv + q] = Ff[(size_t)cf[t] * nv + q];
+                Gl[t * nv + q] = Gf[(size_t)cf[t] * nv + q];
+            }
+            al[t] = af[cf[t]];
+        }
+        gather_cell(c, i, Fl.data(), Gl.data(), al.data(), &R[(size_t)i * nv], &gnew[(size_t)i * nv * dim],
+                    &anew[i]);
+    }
+}
+
+/* The same residual for a sample of cells only: the reconstructions of the
+ * cells and of their face neighbours, the sums of the cells' faces and the
+ * gather, by the routines above (so the values equal those of
+ * fine_residual); for checking large meshes cell by cell. */
+static void fine_residual_cells(orc_ctx* c, const int* cells, int m, double* R, double* gnew, double* anew) {
+    const int dim = c->dim, nv = c->nvar;
+    Level& L0 = c->lv[0];
+    std::vector<double> dte, dti;
+    time_steps(c, 0, L0.W, dte, dti);
+    std::vector<int> need;
+    for (int s = 0; s < m; ++s) {
+        const int i = cells[s];
+        need.push_back(i);
         for (int fi : L0.cf[i]) {
             const Face& f = L0.faces[fi];
-            double sg = (f.L == i) ? 1.0 : -1.0;
-            for (int q = 0; q < nv; ++q) R[i * nv + q] += sg * Ff[fi * nv + q];
-            anew[i] *= af[fi];
+            need.push_back(f.L == i ? f.R : f.L);
         }
-        for (int fi : L0.cf[i]) {
-            const Face& f = L0.faces[fi];
-            double n[3];
-            outward(f, i, dim, n);
-            for (int q = 0; q < nv; ++q)
-                for (int d = 0; d < dim; ++d) gnew[(i * nv + q) * dim + d] += f.S * Gf[fi * nv + q] * n[d];
+    }
+    std::sort(need.begin(), need.end());
+    need.erase(std::unique(need.begin(), need.end()), need.end());
+    if (!need.empty() && need.front() < 0) need.erase(need.begin());
+    std::vector<CellRec> rec(need.size());
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < need.size(); ++k) build_rec(c, need[k], rec[k]);
+    auto find = [&](int j) -> const CellRec& {
+        return rec[std::lower_bound(need.begin(), need.end(), j) - need.begin()];
+    };
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < m; ++s) {
+        const int i = cells[s];
+        const std::vector<int>& cf = L0.cf[i];
+        std::vector<double> Fl(cf.size() * nv), Gl(cf.size() * nv), al(cf.size());
+        for (size_t t = 0; t < cf.size(); ++t) {
+            const Face& f = L0.faces[cf[t]];
+            double dt = dte[f.L];
+            if (f.R >= 0) dt = std::min(dt, dte[f.R]);
+            face_sums(c, f, find(f.L), f.R >= 0 ? &find(f.R) : nullptr, dt, &Fl[t * nv], &Gl[t * nv], &al[t]);
         }
-        for (int q = 0; q < nv; ++q)
-            for (int d = 0; d < dim; ++d) gnew[(i * nv + q) * dim + d] *= anew[i] / L0.V[i];
+        gather_cell(c, i, Fl.data(), Gl.data(), al.data(), &R[(size_t)s * nv], &gnew[(size_t)s * nv * dim],
+                    &anew[s]);
     }
 }
 
@@ -772,6 +851,18 @@ int orc_residual(orc_ctx* c, int level, double* R, double* gradW_new, double* al
     if (R)
         for (size_t k = 0; k < Res.size(); ++k) R[k] = -(Res[k] + L.F[k]);
     if (alpha_out) std::copy(L.alpha.begin(), L.alpha.end(), alpha_out);
+    return ORC_OK;
+}
+
+/* Fine residual, evolved slopes and DF of the m listed cells (original
+ * order indices; outputs [m][nvar], [m][nvar][dim], [m]). */
+int orc_residual_cells(orc_ctx* c, const int* cells, int m, double* R, double* gradW_new, double* alpha_out) {
+    int rc = check(c, 0);
+    if (rc) return rc;
+    if (m < 0 || (m > 0 && (!cells || !R || !gradW_new || !alpha_out))) return ORC_EINVAL;
+    for (int s = 0; s < m; ++s)
+        if (cells[s] < 0 || cells[s] >= c->lv[0].n) return ORC_EINVAL;
+    fine_residual_cells(c, cells, m, R, gradW_new, alpha_out);
     return ORC_OK;
 }
 

@@ -539,3 +539,30 @@ def test_slip_wall_p1_option_acts_on_slip_wall_cells_only(orc):
     changed = set(np.nonzero(np.any(R0 != R1, axis=1))[0].tolist())
     assert changed and changed <= near
     assert wall_cells <= changed
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sampled_residual_equals_full_residual(orc, dim):
+    """orc_residual_cells (the residual of a sample of cells, for checking meshes
+    too large for the whole residual) equals the full residual's rows bit for
+    bit, boundary cells included."""
+    if dim == 2:
+        mesh = sm.annulus(12, 4, jitter=0.15, seed=3, nref=1, wall_tag=sm.ISOTHERMAL)
+        prm = dict(mach=0.5, reynolds=100.0)
+    else:
+        mesh = sm.sphere_shell_kuhn(4, 2, 2, nref=1)
+        prm = dict(dim=3, mach=2.0)
+    o = orc.Oracle(mesh, n_levels=1, **prm)
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(4)
+    W, _, _ = o.get_state()
+    o.init_freestream()
+    W, _, _ = o.get_state()
+    W = W * (1.0 + 0.02 * rng.standard_normal(W.shape[0]))[:, None]
+    grad = 1e-3 * rng.standard_normal((mesh.n_cells, dim + 2, dim))
+    alpha = rng.uniform(0.5, 1.0, mesh.n_cells)
+    o.set_state(W, grad, alpha)
+    R, g, a = o.residual(0)
+    cells = np.unique(np.concatenate([rng.choice(mesh.n_cells, 40, replace=False), [0, mesh.n_cells - 1]]))
+    Rs, gs, as_ = o.residual_cells(cells)
+    assert np.array_equal(Rs, R[cells]) and np.array_equal(gs, g[cells]) and np.array_equal(as_, a[cells])
