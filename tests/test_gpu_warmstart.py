@@ -46,6 +46,10 @@ def test_warm_start_needs_fewer_cycles(cg):
     _, cold, s_cold, _ = ws.batched_solve(test, tol, maxc)
     warm_solvers, warm, s_warm, _ = ws.batched_solve(test, tol, maxc, init=ws.warm_init(net, scaling))
     both = np.array([a == cg.OK and b == cg.OK for a, b in zip(s_cold, s_warm)])
+    n_cold, n_warm = sum(s == cg.OK for s in s_cold), sum(s == cg.OK for s in s_warm)
+    print(f"converged: cold {n_cold} of 8, warm {n_warm} of 8", flush=True)
+    # the warm start may not lose problems the free-stream start solves
+    assert n_warm >= n_cold
     assert both.sum() >= 4
     c, w = np.asarray(cold)[both], np.asarray(warm)[both]
     print(f"cycles to 1e-10 on {both.sum()} problems: cold {c.mean():.0f}, warm {w.mean():.0f}", flush=True)
