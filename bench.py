@@ -62,8 +62,8 @@ RECON_BYTES_PER_CELL = {
 # counter's reading for a plain device copy of known size.  Valid only for the
 # kernel source the counters were taken with; absent (null) otherwise.
 TRAFFIC_BYTES = {
-    # FETCH_SIZE 3,933,000 KiB x 2.0 + WRITE_SIZE 1,983,700 KiB x 1.0, median per launch
-    ("sphere_euler_mach6_3.1M", "k_recon<3, 16>"): (3.9330e6 * 2.0 + 1.9837e6 * 1.0) * 1024,
+    # FETCH_SIZE 3,938,100 KiB x 2.0 + WRITE_SIZE 1,983,700 KiB x 1.0, median per launch
+    ("sphere_euler_mach6_3.1M", "k_recon<3, 16>"): (3.9381e6 * 2.0 + 1.9837e6 * 1.0) * 1024,
 }
 
 # FP64 operations the flux kernel executes per face Gauss point, from the
