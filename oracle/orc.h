@@ -64,6 +64,12 @@ typedef struct orc_mesh {
     int n_bfaces;
     const int32_t* bface_nodes;/* [n_bfaces][dim] */
     const int32_t* bface_tag;  /* [n_bfaces] */
+    /* 3-D mixed elements (both NULL for simplex meshes): cell i is
+     * cell_nodes[cell_offsets[i] .. cell_offsets[i+1]) with 4, 5, 6 or 8 nodes
+     * (tetrahedron, pyramid with its base first, prism, hexahedron), boundary
+     * face b is bface_nodes[bface_offsets[b] .. bface_offsets[b+1]) */
+    const int32_t* cell_offsets;
+    const int32_t* bface_offsets;
 } orc_mesh;
 
 typedef struct orc_ctx orc_ctx;
@@ -82,6 +88,9 @@ int orc_level_size(orc_ctx* c, int level, int* n_cells, int* n_faces);
 
 int orc_cell_geometry(orc_ctx* c, int level, double* V, double* C);
 int orc_face_geometry(orc_ctx* c, int level, int32_t* LR, int32_t* tag, double* n, double* S, double* xc);
+/* Gauss points of every fine face, [n_faces][4][dim], their weights
+ * [n_faces][4] (summing to 1; unused entries 0) and counts [n_faces]. */
+int orc_face_quadrature(orc_ctx* c, int32_t* ngp, double* gp, double* w);
 
 int orc_coloring(orc_ctx* c, int level, int32_t* color_out, int32_t* n_colors);
 int orc_coloring_graph(int n, const int32_t* xadj, const int32_t* adj, int32_t* color_out, int32_t* n_colors);

@@ -46,7 +46,8 @@ class OrcMesh(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_nodes", C.c_int), ("coords", C.POINTER(C.c_double)),
                 ("n_cells", C.c_int), ("cell_nodes", C.POINTER(C.c_int32)),
                 ("n_bfaces", C.c_int), ("bface_nodes", C.POINTER(C.c_int32)),
-                ("bface_tag", C.POINTER(C.c_int32))]
+                ("bface_tag", C.POINTER(C.c_int32)),
+                ("cell_offsets", C.POINTER(C.c_int32)), ("bface_offsets", C.POINTER(C.c_int32))]
 
 
 def build():
@@ -114,6 +115,10 @@ class Oracle:
                       np.ascontiguousarray(mesh.btags, dtype=np.int32)]
         m = OrcMesh(mesh.dim, mesh.n_nodes, _dp(self._keep[0]), mesh.n_cells, _ip(self._keep[1]),
                     len(mesh.btags), _ip(self._keep[2]), _ip(self._keep[3]))
+        if getattr(mesh, "cell_offsets", None) is not None:
+            self._keep += [np.ascontiguousarray(mesh.cell_offsets, dtype=np.int32),
+                           np.ascontiguousarray(mesh.bface_offsets, dtype=np.int32)]
+            m.cell_offsets, m.bface_offsets = _ip(self._keep[4]), _ip(self._keep[5])
         par = (C.POINTER(C.c_int32) * max(n_levels - 1, 1))()
         pk = []
         for l in range(n_levels - 1):
@@ -165,6 +170,14 @@ class Oracle:
         xc = np.zeros((nf, self.dim))
         self._chk(lib().orc_face_geometry(self.ctx, level, _ip(LR), _ip(tag), _dp(n), _dp(S), _dp(xc)))
         return dict(LR=LR, tag=tag, n=n, S=S, xc=xc)
+
+    def face_quadrature(self):
+        nf = self.sizes[0][1]
+        ngp = np.zeros(nf, dtype=np.int32)
+        gp = np.zeros((nf, 4, self.dim))
+        w = np.zeros((nf, 4))
+        self._chk(lib().orc_face_quadrature(self.ctx, _ip(ngp), _dp(gp), _dp(w)))
+        return ngp, gp, w
 
     def coloring(self, level):
         n = self.sizes[level][0]

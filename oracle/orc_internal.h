@@ -31,9 +31,9 @@ struct Face {
     double n[3];     /* unit normal, L -> R (outward from L) */
     double S;        /* area (length in 2-D) */
     double xc[3];    /* face centre */
-    int ngp;
-    double gp[3][3];
-    double w[3];
+    int ngp;         /* 2 (edge), 3 (triangle) or 4 (quadrilateral) */
+    double gp[4][3];
+    double w[4];     /* weights of the Gauss points, summing to 1 */
 };
 
 struct Level {
@@ -46,7 +46,8 @@ struct Level {
     std::vector<int> color;          /* 1..ncolor (coarse levels) */
     int ncolor = 0;
     /* fine level only */
-    std::vector<int> nodes;          /* [n][dim+1] */
+    std::vector<int> nodes;          /* [n][dim+1]; mixed elements: flat, cell i at noff[i] */
+    std::vector<int> noff;           /* mixed elements only: [n+1] offsets into nodes */
     std::vector<double> h;           /* basis scale V^(1/dim) */
     /* state */
     std::vector<double> W, W0, F, Rstar, alpha, grad, dW;
@@ -74,6 +75,7 @@ struct orc_ctx {
     long long guard_hits = 0, prolong_skips = 0;
     long long cycles = 0;          /* V-cycles begun since the state was last set */
     bool have_mesh = false;
+    bool mixed = false;            /* 3-D mixed-element input (noff set) */
 };
 
 namespace orc {
@@ -87,6 +89,14 @@ void basis_exps(int dim, int k, int* e);
 double basis_eval(int dim, int k, const double* x, const double* x0, double h);
 double basis_deriv(int dim, int k, const int* l, const double* x, const double* x0, double h);
 void cell_quadrature(const orc_ctx* c, int cell, std::vector<double>& pts, std::vector<double>& wts);
+struct ElemFaces {
+    int nf;          /* faces */
+    int nn[6];       /* nodes of each face */
+    int v[6][4];     /* local node cycle of each face */
+};
+const ElemFaces* elem_faces(int nnodes);
+void mixed_cell(const orc_ctx* c, int cell, double* V, double* C, std::vector<double>* pts,
+                std::vector<double>* wts);
 }  // namespace orc
 
 #endif

@@ -46,8 +46,98 @@ double basis_deriv(int dim, int k, const int* l, const double* x, const double* 
     return v;
 }
 
-/* Degree-2-exact average rule over a fine simplex: weights sum to 1. */
+/* Local faces of the 3-D element types (Sec. 2.2: 4, 5, 5 and 6 faces) as
+ * node cycles of the input node order: tetrahedron face k is the one
+ * opposite node k; pyramid: the base, then the four triangles; prism: the
+ * two triangles, then the three quadrilaterals; hexahedron: the two
+ * quadrilaterals given first and last, then the four sides. */
+const ElemFaces* elem_faces(int nnodes) {
+    static const ElemFaces tet = {4, {3, 3, 3, 3, 0, 0}, {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}}};
+    static const ElemFaces pyr = {5, {4, 3, 3, 3, 3, 0},
+                                  {{0, 1, 2, 3}, {0, 1, 4}, {1, 2, 4}, {2, 3, 4}, {3, 0, 4}}};
+    static const ElemFaces pri = {5, {3, 3, 4, 4, 4, 0},
+                                  {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}}};
+    static const ElemFaces hex = {6, {4, 4, 4, 4, 4, 4},
+                                  {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}}};
+    switch (nnodes) {
+        case 4: return &tet;
+        case 5: return &pyr;
+        case 6: return &pri;
+        case 8: return &hex;
+        default: return nullptr;
+    }
+}
+
+/* A mixed element with planar faces is the union of the cones from the
+ * average of its nodes to the triangles of its faces (quadrilateral a, b, c,
+ * d: triangles a, b, c and a, c, d).  Volume and centroid are the sums over
+ * the cones; the average rule is the symmetric 4-point rule of every cone
+ * (exact for quadratics) weighted by the cone's share of the volume. */
+void mixed_cell(const orc_ctx* c, int cell, double* Vout, double* Cout, std::vector<double>* pts,
+                std::vector<double>* wts) {
+    const Level& L0 = c->lv[0];
+    const int* nd = &L0.nodes[L0.noff[cell]];
+    const int nn = L0.noff[cell + 1] - L0.noff[cell];
+    const ElemFaces* ef = elem_faces(nn);
+    const double* X = c->coords.data();
+    double xm[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < nn; ++j)
+        for (int d = 0; d < 3; ++d) xm[d] += X[nd[j] * 3 + d];
+    for (int d = 0; d < 3; ++d) xm[d] /= nn;
+    std::vector<std::array<double, 12>> cone;   /* apex xm, then a, b, e */
+    std::vector<double> vol;
+    double V = 0.0, M[3] = {0.0, 0.0, 0.0};
+    for (int f = 0; f < ef->nf; ++f)
+        for (int t = 0; t + 2 < ef->nn[f]; ++t) {
+            const double* a = X + nd[ef->v[f][0]] * 3;
+            const double* b = X + nd[ef->v[f][t + 1]] * 3;
+            const double* e = X + nd[ef->v[f][t + 2]] * 3;
+            double u[3], v[3], w[3];
+            for (int d = 0; d < 3; ++d) {
+                u[d] = a[d] - xm[d];
+                v[d] = b[d] - xm[d];
+                w[d] = e[d] - xm[d];
+            }
+            const double det = u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                               u[2] * (v[0] * w[1] - v[1] * w[0]);
+            const double cv = std::fabs(det) / 6.0;
+            std::array<double, 12> P;
+            for (int d = 0; d < 3; ++d) {
+                P[d] = xm[d];
+                P[3 + d] = a[d];
+                P[6 + d] = b[d];
+                P[9 + d] = e[d];
+                M[d] += cv * (xm[d] + a[d] + b[d] + e[d]) / 4.0;
+            }
+            cone.push_back(P);
+            vol.push_back(cv);
+            V += cv;
+        }
+    if (Vout) *Vout = V;
+    if (Cout)
+        for (int d = 0; d < 3; ++d) Cout[d] = M[d] / V;
+    if (pts) {
+        pts->clear();
+        wts->clear();
+        const double A = 0.5854101966249685, B = 0.1381966011250105;
+        for (size_t t = 0; t < cone.size(); ++t)
+            for (int k = 0; k < 4; ++k) {
+                for (int d = 0; d < 3; ++d) {
+                    double s = 0.0;
+                    for (int j = 0; j < 4; ++j) s += (j == k ? A : B) * cone[t][j * 3 + d];
+                    pts->push_back(s);
+                }
+                wts->push_back(0.25 * vol[t] / V);
+            }
+    }
+}
+
+/* Degree-2-exact average rule over a fine cell: weights sum to 1. */
 void cell_quadrature(const orc_ctx* c, int cell, std::vector<double>& pts, std::vector<double>& wts) {
+    if (c->mixed) {
+        mixed_cell(c, cell, nullptr, nullptr, &pts, &wts);
+        return;
+    }
     const int dim = c->dim;
     const Level& L0 = c->lv[0];
     const int* nd = &L0.nodes[cell * (dim + 1)];
@@ -162,6 +252,68 @@ void face_geometry(const orc_ctx* c, const std::vector<int>& key, const double* 
     for (int d = 0; d < dim; ++d) dot += f.n[d] * (f.xc[d] - CL[d]);
     if (dot < 0.0)
         for (int d = 0; d < dim; ++d) f.n[d] = -f.n[d];
+}
+
+/* Geometry of a planar quadrilateral face with node cycle a, b, e, g: area
+ * vector (e - a) x (g - b) / 2, centroid from the triangles a, b, e and
+ * a, e, g, and the 2 x 2 Gauss rule of its bilinear map from [-1, 1]^2, each
+ * point weighted by the map's area element there (the weights sum to 1).
+ * False when the fourth node is off the plane of the first three. */
+bool quad_face_geometry(const orc_ctx* c, const int* cyc, const double* CL, Face& f) {
+    const double* X = c->coords.data();
+    const double *a = X + cyc[0] * 3, *b = X + cyc[1] * 3, *e = X + cyc[2] * 3, *g = X + cyc[3] * 3;
+    auto cross = [](const double* u, const double* v, double* w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    auto norm = [](const double* u) { return std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); };
+    double p[3], q[3], N[3];
+    for (int d = 0; d < 3; ++d) {
+        p[d] = e[d] - a[d];
+        q[d] = g[d] - b[d];
+    }
+    cross(p, q, N);
+    const double nn = norm(N);
+    f.S = 0.5 * nn;
+    for (int d = 0; d < 3; ++d) f.n[d] = N[d] / nn;
+    double off = 0.0;
+    for (int d = 0; d < 3; ++d) off += (g[d] - a[d]) * f.n[d];
+    if (std::fabs(off) > 1e-9 * std::sqrt(f.S)) return false;
+    double u1[3], v1[3], w1[3], u2[3], w2[3];
+    for (int d = 0; d < 3; ++d) {
+        u1[d] = b[d] - a[d];
+        v1[d] = e[d] - a[d];
+        u2[d] = g[d] - a[d];
+    }
+    cross(u1, v1, w1);
+    cross(v1, u2, w2);
+    const double A1 = 0.5 * norm(w1), A2 = 0.5 * norm(w2);
+    for (int d = 0; d < 3; ++d)
+        f.xc[d] = (A1 * (a[d] + b[d] + e[d]) / 3.0 + A2 * (a[d] + e[d] + g[d]) / 3.0) / (A1 + A2);
+    f.ngp = 4;
+    const double r = 1.0 / std::sqrt(3.0);
+    const double sp[4] = {-r, r, r, -r}, tp[4] = {-r, -r, r, r};
+    double jac[4], jsum = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double s = sp[k], t = tp[k];
+        double xs[3], xt[3], J[3];
+        for (int d = 0; d < 3; ++d) {
+            f.gp[k][d] = 0.25 * ((1 - s) * (1 - t) * a[d] + (1 + s) * (1 - t) * b[d] + (1 + s) * (1 + t) * e[d] +
+                                 (1 - s) * (1 + t) * g[d]);
+            xs[d] = 0.25 * (-(1 - t) * a[d] + (1 - t) * b[d] + (1 + t) * e[d] - (1 + t) * g[d]);
+            xt[d] = 0.25 * (-(1 - s) * a[d] - (1 + s) * b[d] + (1 + s) * e[d] + (1 - s) * g[d]);
+        }
+        cross(xs, xt, J);
+        jac[k] = norm(J);
+        jsum += jac[k];
+    }
+    for (int k = 0; k < 4; ++k) f.w[k] = jac[k] / jsum;
+    double dot = 0.0;
+    for (int d = 0; d < 3; ++d) dot += f.n[d] * (f.xc[d] - CL[d]);
+    if (dot < 0.0)
+        for (int d = 0; d < 3; ++d) f.n[d] = -f.n[d];
+    return true;
 }
 
 /* Faces of an agglomerated level: one face per pair of adjacent agglomerates and
@@ -475,22 +627,44 @@ int setup_mesh(orc_ctx* c, const orc_mesh* m, int n_levels, const int32_t* const
     const int dim = m->dim;
     if (dim != c->p.dim || (dim != 2 && dim != 3)) return fail(c, ORC_EINVAL, "dimension mismatch");
     if (n_levels < 1) return fail(c, ORC_EINVAL, "n_levels < 1");
+    const bool mixed = m->cell_offsets != nullptr;
+    if (mixed != (m->bface_offsets != nullptr))
+        return fail(c, ORC_EINVAL, "cell_offsets and bface_offsets go together");
+    if (mixed && dim != 3) return fail(c, ORC_EINVAL, "mixed elements are 3-D only");
+    c->mixed = mixed;
     c->dim = dim;
     c->nvar = dim + 2;
     c->coords.assign(m->coords, m->coords + (size_t)m->n_nodes * dim);
     c->lv.assign(n_levels, Level());
     Level& L0 = c->lv[0];
     L0.n = m->n_cells;
-    L0.nodes.assign(m->cell_nodes, m->cell_nodes + (size_t)m->n_cells * (dim + 1));
+    if (mixed) {
+        L0.noff.assign(m->cell_offsets, m->cell_offsets + m->n_cells + 1);
+        if (L0.noff[0] != 0) return fail(c, ORC_EMESH, "cell_offsets[0] != 0");
+        for (int i = 0; i < L0.n; ++i)
+            if (!elem_faces(L0.noff[i + 1] - L0.noff[i]))
+                return fail(c, ORC_EMESH, "cell with a node count other than 4, 5, 6 or 8");
+        L0.nodes.assign(m->cell_nodes, m->cell_nodes + L0.noff[L0.n]);
+    } else {
+        L0.nodes.assign(m->cell_nodes, m->cell_nodes + (size_t)m->n_cells * (dim + 1));
+    }
+    auto cell_nodes = [&](int i, int& cnt) -> const int* {
+        cnt = mixed ? L0.noff[i + 1] - L0.noff[i] : dim + 1;
+        return mixed ? &L0.nodes[L0.noff[i]] : &L0.nodes[(size_t)i * (dim + 1)];
+    };
     L0.V.resize(L0.n);
     L0.C.resize((size_t)L0.n * dim);
     L0.h.resize(L0.n);
     for (int i = 0; i < L0.n; ++i) {
-        const int* nd = &L0.nodes[i * (dim + 1)];
-        for (int j = 0; j <= dim; ++j)
+        int cnt;
+        const int* nd = cell_nodes(i, cnt);
+        for (int j = 0; j < cnt; ++j)
             if (nd[j] < 0 || nd[j] >= m->n_nodes) return fail(c, ORC_EMESH, "node id out of range");
         double C[3];
-        simplex_geometry(c, nd, &L0.V[i], C);
+        if (mixed)
+            mixed_cell(c, i, &L0.V[i], C, nullptr, nullptr);
+        else
+            simplex_geometry(c, nd, &L0.V[i], C);
         if (!(L0.V[i] > 0.0)) return fail(c, ORC_EMESH, "non-positive cell volume");
         for (int d = 0; d < dim; ++d) L0.C[i * dim + d] = C[d];
         L0.h[i] = (dim == 2) ? std::sqrt(L0.V[i]) : std::cbrt(L0.V[i]);
@@ -498,17 +672,41 @@ int setup_mesh(orc_ctx* c, const orc_mesh* m, int n_levels, const int32_t* const
     /* Canonical faces: sorted node tuples in lexicographic order. */
     std::vector<std::tuple<std::vector<int>, int, int>> all;
     all.reserve((size_t)L0.n * (dim + 1));
-    for (int i = 0; i < L0.n; ++i)
-        for (int k = 0; k <= dim; ++k) all.emplace_back(face_key(&L0.nodes[i * (dim + 1)], dim, k), i, k);
+    /* node cycle of local face k of cell i */
+    auto face_cycle = [&](int i, int k) {
+        int cnt;
+        const int* nd = cell_nodes(i, cnt);
+        std::vector<int> cyc;
+        if (mixed) {
+            const ElemFaces* ef = elem_faces(cnt);
+            for (int j = 0; j < ef->nn[k]; ++j) cyc.push_back(nd[ef->v[k][j]]);
+        } else {
+            cyc = face_key(nd, dim, k);
+        }
+        return cyc;
+    };
+    L0.cf.assign(L0.n, std::vector<int>());
+    for (int i = 0; i < L0.n; ++i) {
+        int cnt;
+        cell_nodes(i, cnt);
+        const int nfc = mixed ? elem_faces(cnt)->nf : dim + 1;
+        L0.cf[i].assign(nfc, -1);
+        for (int k = 0; k < nfc; ++k) {
+            std::vector<int> key = face_cycle(i, k);
+            std::sort(key.begin(), key.end());
+            all.emplace_back(key, i, k);
+        }
+    }
     std::sort(all.begin(), all.end());
     std::vector<std::pair<std::vector<int>, int>> bkeys;
     for (int b = 0; b < m->n_bfaces; ++b) {
-        std::vector<int> key(m->bface_nodes + (size_t)b * dim, m->bface_nodes + (size_t)(b + 1) * dim);
+        const size_t b0 = mixed ? (size_t)m->bface_offsets[b] : (size_t)b * dim;
+        const size_t b1 = mixed ? (size_t)m->bface_offsets[b + 1] : (size_t)(b + 1) * dim;
+        std::vector<int> key(m->bface_nodes + b0, m->bface_nodes + b1);
         std::sort(key.begin(), key.end());
         bkeys.emplace_back(key, m->bface_tag[b]);
     }
     std::sort(bkeys.begin(), bkeys.end());
-    L0.cf.assign(L0.n, std::vector<int>(dim + 1, -1));
     int nbmatched = 0;
     for (size_t s = 0; s < all.size();) {
         size_t e = s + 1;
@@ -526,7 +724,15 @@ int setup_mesh(orc_ctx* c, const orc_mesh* m, int n_levels, const int32_t* const
             f.tag = it->second;
             ++nbmatched;
         }
-        face_geometry(c, key, &L0.C[f.L * dim], f);
+        if (!mixed) {
+            face_geometry(c, key, &L0.C[f.L * dim], f);
+        } else {
+            const std::vector<int> cyc = face_cycle(std::get<1>(all[s]), std::get<2>(all[s]));
+            if (cyc.size() == 3)
+                face_geometry(c, cyc, &L0.C[f.L * dim], f);
+            else if (!quad_face_geometry(c, cyc.data(), &L0.C[f.L * dim], f))
+                return fail(c, ORC_EMESH, "non-planar quadrilateral face");
+        }
         int fi = (int)L0.faces.size();
         L0.faces.push_back(f);
         for (size_t t = s; t < e; ++t) L0.cf[std::get<1>(all[t])][std::get<2>(all[t])] = fi;

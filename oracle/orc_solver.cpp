@@ -752,6 +752,21 @@ int orc_face_geometry(orc_ctx* c, int level, int32_t* LR, int32_t* tag, double* 
     return ORC_OK;
 }
 
+int orc_face_quadrature(orc_ctx* c, int32_t* ngp, double* gp, double* w) {
+    int rc = check(c, 0);
+    if (rc) return rc;
+    const Level& L = c->lv[0];
+    for (size_t f = 0; f < L.faces.size(); ++f) {
+        ngp[f] = L.faces[f].ngp;
+        for (int k = 0; k < 4; ++k) {
+            w[f * 4 + k] = k < L.faces[f].ngp ? L.faces[f].w[k] : 0.0;
+            for (int d = 0; d < c->dim; ++d)
+                gp[(f * 4 + k) * c->dim + d] = k < L.faces[f].ngp ? L.faces[f].gp[k][d] : 0.0;
+        }
+    }
+    return ORC_OK;
+}
+
 int orc_coloring(orc_ctx* c, int level, int32_t* color_out, int32_t* n_colors) {
     int rc = check(c, level);
     if (rc) return rc;

@@ -29,11 +29,16 @@ ADIABATIC = 4
 
 @dataclass
 class Mesh:
-    """A simplex mesh with boundary faces and refinement parent maps.
+    """A mesh with boundary faces and refinement parent maps.
 
     coords      float64 [n_nodes, dim]
-    cells       int32   [n_cells, dim+1], positively oriented
-    bfaces      int32   [n_bfaces, dim]   node ids of boundary faces
+    cells       int32   [n_cells, dim+1], positively oriented simplices; or,
+                when cell_offsets is given (3-D mixed elements), the flat node
+                list of every cell, cell i being cells[cell_offsets[i]:
+                cell_offsets[i+1]] (4, 5, 6 or 8 nodes: tetrahedron, pyramid,
+                prism, hexahedron in the node orders of ELEMENT_ORDER)
+    bfaces      int32   [n_bfaces, dim]   node ids of boundary faces; or flat
+                (3 or 4 nodes each) when bface_offsets is given
     btags       int32   [n_bfaces]
     parents     list of int32 arrays; parents[l][i] is the index, on level
                 l+1, of the agglomerate that contains cell i of level l.
@@ -47,9 +52,13 @@ class Mesh:
     btags: np.ndarray
     parents: list = field(default_factory=list)
     info: dict = field(default_factory=dict)
+    cell_offsets: np.ndarray = None
+    bface_offsets: np.ndarray = None
 
     @property
     def n_cells(self) -> int:
+        if self.cell_offsets is not None:
+            return int(len(self.cell_offsets) - 1)
         return int(self.cells.shape[0])
 
     @property
@@ -524,6 +533,126 @@ def sphere_shell_kuhn(n_az, n_pol, n_rad, r_in=0.5, r_out=6.0, q=1.2, nref=2,
                 np.ascontiguousarray(bf, dtype=np.int32), btags, parents,
                 dict(kind="sphere_shell_kuhn", n_az=n_az, n_pol=n_pol, n_rad=n_rad, r_in=r_in, r_out=r_out,
                      q=q, nref=nref))
+
+
+# Mixed-element meshes -----------------------------------------------------
+
+ELEMENT_ORDER = """Node orders of the mixed-element input format:
+tetrahedron (4 nodes) any order; pyramid (5): the base quadrilateral in
+cyclic order, then the apex; prism (6): one triangle, then the other with
+node 3+k joined to node k by an edge; hexahedron (8): one quadrilateral in
+cyclic order, then the opposite one with node 4+k joined to node k."""
+
+
+def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tags=None):
+    """Box of n^3 cubes (n even) filled with all four 3-D element types.
+
+    The grid lines of each axis are spaced by seeded factors in
+    [1 - grade, 1 + grade] on [0, 1]; then the frustum map scales x and y
+    about 0.5 by (1 + taper z), which keeps every face planar (the faces of
+    constant x or y become trapezoids, the hexahedra non-affine).  Columns
+    (i, j) drawn with probability p_prism are cut into two prisms per cube
+    along the diagonal from corner (i, j) to (i+1, j+1); in the other columns
+    vertical pairs of cubes (k, k+1), k even, drawn with probability
+    p_pyramid, become six pyramids each (apex at a new node at the cube's
+    centre), and the two pyramids on the quadrilateral the pair shares are
+    cut into two tetrahedra each along the same diagonal; every other cube is
+    a hexahedron.  Cells are numbered cube by cube and cubes block by block
+    of 2 x 2 x 2, so parents[0] maps a cell to its cube and parents[1] a cube
+    to its block.  tags maps a side ('x0', 'x1', 'y0', 'y1', 'z0', 'z1') to
+    its boundary tag (default far field).  Node orders: ELEMENT_ORDER."""
+    if n % 2:
+        raise ValueError("n must be even")
+    rng = np.random.default_rng(seed)
+    side_tag = {k: FARFIELD for k in ("x0", "x1", "y0", "y1", "z0", "z1")}
+    side_tag.update(tags or {})
+
+    def axis():
+        w = rng.uniform(1.0 - grade, 1.0 + grade, size=n)
+        g = np.concatenate([[0.0], np.cumsum(w)]) / w.sum()
+        g[-1] = 1.0
+        return g
+
+    gx, gy, gz = axis(), axis(), axis()
+    prism_col = rng.random((n, n)) < p_prism
+    pyr_pair = rng.random((n, n, n // 2)) < p_pyramid
+    X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
+    ijk = [(i, j, k) for i in range(n + 1) for j in range(n + 1) for k in range(n + 1)]
+    unit = [np.array([X[t], Y[t], Z[t]]) for t in ijk]       # before the frustum map
+    nidx = {t: m for m, t in enumerate(ijk)}
+    cells, sides = [], []
+
+    def centre_node(i, j, k):
+        unit.append(np.array([0.5 * (gx[i] + gx[i + 1]), 0.5 * (gy[j] + gy[j + 1]), 0.5 * (gz[k] + gz[k + 1])]))
+        return len(unit) - 1
+
+    cube_of = []
+    for bk in range(n // 2):
+        for bj in range(n // 2):
+            for bi in range(n // 2):
+                for c in range(8):
+                    i, j, k = 2 * bi + (c & 1), 2 * bj + ((c >> 1) & 1), 2 * bk + ((c >> 2) & 1)
+                    v = [nidx[(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1))] for a in range(8)]
+                    bot, top = [v[0], v[1], v[3], v[2]], [v[4], v[5], v[7], v[6]]
+                    cube = (bk * (n // 2) + bj) * (n // 2) + bi
+                    cube = cube * 8 + c
+                    if prism_col[i, j]:
+                        new = [[v[0], v[1], v[3], v[4], v[5], v[7]], [v[0], v[3], v[2], v[4], v[7], v[6]]]
+                    elif pyr_pair[i, j, k // 2]:
+                        cn = centre_node(i, j, k)
+                        quads = [bot, top, [v[0], v[1], v[5], v[4]], [v[1], v[3], v[7], v[5]],
+                                 [v[3], v[2], v[6], v[7]], [v[2], v[0], v[4], v[6]]]
+                        shared = 1 if k % 2 == 0 else 0     # the face towards the pair's other cube
+                        new = []
+                        for f, q in enumerate(quads):
+                            if f == shared:
+                                new += [[q[0], q[1], q[2], cn], [q[0], q[2], q[3], cn]]
+                            else:
+                                new.append(q + [cn])
+                    else:
+                        new = [bot + top]
+                    cells += new
+                    cube_of += [cube] * len(new)
+    unit = np.array(unit)
+    s = 1.0 + taper * unit[:, 2]
+    xyz = np.stack([(unit[:, 0] - 0.5) * s + 0.5, (unit[:, 1] - 0.5) * s + 0.5, unit[:, 2]], axis=1)
+    # boundary faces: cell faces that occur once (local face tables of the node orders)
+    ftab = {4: [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)],
+            5: [(0, 1, 2, 3), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)],
+            6: [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
+            8: [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]}
+    count = {}
+    for cell in cells:
+        for f in ftab[len(cell)]:
+            key = tuple(sorted(cell[a] for a in f))
+            count[key] = count.get(key, (0, [cell[a] for a in f]))
+            count[key] = (count[key][0] + 1, count[key][1])
+    bfaces, btags = [], []
+    tol = 1e-12
+    for key, (cnt, nodes) in count.items():
+        if cnt != 1:
+            continue
+        u = unit[list(nodes)]
+        for d, ax in enumerate("xyz"):
+            if np.all(np.abs(u[:, d]) < tol):
+                btags.append(side_tag[ax + "0"])
+                break
+            if np.all(np.abs(u[:, d] - 1.0) < tol):
+                btags.append(side_tag[ax + "1"])
+                break
+        else:
+            raise ValueError("boundary face off the box")
+        bfaces.append(nodes)
+    coff = np.concatenate([[0], np.cumsum([len(c) for c in cells])]).astype(np.int32)
+    boff = np.concatenate([[0], np.cumsum([len(f) for f in bfaces])]).astype(np.int32)
+    parents = [np.array(cube_of, dtype=np.int32), (np.arange(n ** 3, dtype=np.int32) // 8)]
+    kinds = np.bincount(np.diff(coff), minlength=9)
+    return Mesh(3, np.ascontiguousarray(xyz), np.array([v for c in cells for v in c], dtype=np.int32),
+                np.array([v for f in bfaces for v in f], dtype=np.int32), np.array(btags, dtype=np.int32),
+                parents, dict(kind="hybrid_box", n=n, seed=seed, grade=grade, taper=taper,
+                              tets=int(kinds[4]), pyramids=int(kinds[5]), prisms=int(kinds[6]),
+                              hexahedra=int(kinds[8])),
+                cell_offsets=coff, bface_offsets=boff)
 
 
 # Named workloads ----------------------------------------------------------
