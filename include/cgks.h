@@ -72,7 +72,7 @@ extern "C" {
 
 /* Solver parameters.  cgks_default_params() fills the defaults below. */
 typedef struct cgks_params {
-    int dim;                   /* 2 (triangles) or 3 (tetrahedra) */
+    int dim;                   /* 2 (triangles) or 3 (tetrahedra, or hybrid elements: cgks_mesh) */
     double gamma;              /* ratio of specific heats, default 1.4 */
     double prandtl;            /* default 0.72, used when reynolds > 0 */
     double mach;               /* free-stream Mach number */
@@ -139,10 +139,26 @@ typedef struct cgks_mesh {
     int n_nodes;
     const double* coords;      /* [n_nodes][dim] */
     int n_cells;
-    const int32_t* cell_nodes; /* [n_cells][dim+1] */
+    const int32_t* cell_nodes; /* [n_cells][dim+1]; hybrid: flat, see cell_offsets */
     int n_bfaces;
-    const int32_t* bface_nodes;/* [n_bfaces][dim], any node order */
+    const int32_t* bface_nodes;/* [n_bfaces][dim], any node order; hybrid: flat, see bface_offsets */
     const int32_t* bface_tag;  /* [n_bfaces], CGKS_TAG_* */
+    /* 3-D hybrid meshes (Sec. 2.2: tetrahedra, pyramids, prisms and
+     * hexahedra with 4, 5, 5 and 6 faces), or both NULL for simplices.  Cell
+     * i is cell_nodes[cell_offsets[i] .. cell_offsets[i+1]) with 4 nodes (a
+     * tetrahedron, any order), 5 (a pyramid: its base quadrilateral in cyclic
+     * order, then the apex), 6 (a prism: one triangle, then the other with
+     * node 3+k joined to node k) or 8 (a hexahedron: one quadrilateral in
+     * cyclic order, then the opposite one with node 4+k joined to node k);
+     * boundary face b is bface_nodes[bface_offsets[b] .. bface_offsets[b+1])
+     * (3 or 4 nodes, any order).  Every face must be planar (a quadrilateral
+     * more than 1e-9 sqrt(area) off the plane of its first three nodes is
+     * CGKS_EMESH) and every cell convex.  Triangular faces take the 3-point
+     * rule, quadrilaterals the 2 x 2 Gauss rule of their bilinear map with
+     * weights from its area element.  Batched solves take simplex meshes
+     * only. */
+    const int32_t* cell_offsets;  /* [n_cells + 1], cell_offsets[0] = 0 */
+    const int32_t* bface_offsets; /* [n_bfaces + 1] */
 } cgks_mesh;
 
 typedef struct cgks_ctx cgks_ctx;

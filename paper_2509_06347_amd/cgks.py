@@ -46,7 +46,8 @@ class Mesh(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_nodes", C.c_int), ("coords", C.POINTER(C.c_double)),
                 ("n_cells", C.c_int), ("cell_nodes", C.POINTER(C.c_int32)),
                 ("n_bfaces", C.c_int), ("bface_nodes", C.POINTER(C.c_int32)),
-                ("bface_tag", C.POINTER(C.c_int32))]
+                ("bface_tag", C.POINTER(C.c_int32)),
+                ("cell_offsets", C.POINTER(C.c_int32)), ("bface_offsets", C.POINTER(C.c_int32))]
 
 
 _P = C.c_void_p
@@ -163,6 +164,10 @@ class Solver:
         m = Mesh(mesh.dim, mesh.n_nodes, keep[0].ctypes.data_as(_D), mesh.n_cells,
                  keep[1].ctypes.data_as(_I), len(keep[3]), keep[2].ctypes.data_as(_I),
                  keep[3].ctypes.data_as(_I))
+        if getattr(mesh, "cell_offsets", None) is not None:   # hybrid elements
+            keep += [np.ascontiguousarray(mesh.cell_offsets, dtype=np.int32),
+                     np.ascontiguousarray(mesh.bface_offsets, dtype=np.int32)]
+            m.cell_offsets, m.bface_offsets = keep[4].ctypes.data_as(_I), keep[5].ctypes.data_as(_I)
         par = (_I * max(n_levels - 1, 1))()
         for l in range(n_levels - 1):
             if use_parents and l < len(mesh.parents):

@@ -253,8 +253,8 @@ int upload(cgks_ctx* c) {
     std::memset(&f, 0, sizeof(f));
     f.n = H.n;
     f.nf = (int)H.faces.size();
-    f.ngp = (dim == 2) ? 2 : 3;
-    f.nslot = dim + 1;
+    f.ngp = c->hybrid ? 4 : (dim == 2) ? 2 : 3;
+    f.nslot = H.nslot;
     f.nb = (dim == 2) ? 5 : 9;
     const int n = f.n, nf = f.nf, ng = f.ngp, ns = f.nslot, nq = f.nb;
     const int ncol = ns * (1 + dim);
@@ -269,7 +269,7 @@ int upload(cgks_ctx* c) {
     std::vector<int> finv(nf, -1), slotL(nf, 0), slotR(nf, 7);
     fperm.clear();
     for (int i = 0; i < n; ++i)
-        for (int s = 0; s < ns; ++s) {
+        for (int s = 0; s < (int)H.cf[i].size(); ++s) {
             const int k = H.cf[i][s];
             if (H.faces[k].L == i) {
                 slotL[k] = s;
@@ -280,11 +280,15 @@ int upload(cgks_ctx* c) {
             }
         }
     if ((int)fperm.size() != nf) return fail(c, CGKS_EMESH, "face without an owner cell");
-    std::vector<double> fX((size_t)nf * ng * dim);
+    /* mixed elements: a triangle's unused fourth Gauss point repeats its first with weight 0 */
+    std::vector<double> fX((size_t)nf * ng * dim), fw(c->hybrid ? (size_t)nf * ng : 0);
     for (int e = 0; e < nf; ++e) {
         const HFace& F = H.faces[fperm[e]];
-        for (int g = 0; g < ng; ++g)
-            for (int d = 0; d < dim; ++d) fX[((size_t)e * ng + g) * dim + d] = F.gp[g][d];
+        for (int g = 0; g < ng; ++g) {
+            const int gg = g < F.ngp ? g : 0;
+            for (int d = 0; d < dim; ++d) fX[((size_t)e * ng + g) * dim + d] = F.gp[gg][d];
+            if (c->hybrid) fw[(size_t)e * ng + g] = g < F.ngp ? F.w[g] * F.S : 0.0;
+        }
         fL[e] = F.L;
         fR[e] = F.R;
         fS[e] = F.S;
@@ -294,20 +298,24 @@ int upload(cgks_ctx* c) {
     for (int i = 0; i < n; ++i) {
         const double ih = 1.0 / H.h[i];
         for (int s = 0; s < ns; ++s) {
-            const int k = H.cf[i][s];
+            const size_t o = (size_t)s * n + i;
+            const bool empty = s >= (int)H.cf[i].size();   /* mixed elements with fewer than 6 faces */
+            const int k = H.cf[i][empty ? 0 : s];
             const HFace& F = H.faces[k];
             const int side = (F.L == i) ? 0 : 1;
             const double sg = side ? -1.0 : 1.0;
-            const size_t o = (size_t)s * n + i;
-            sface[o] = finv[k] * 2 + side;
-            snbr[o] = (F.R < 0) ? -1 : (side ? F.L : F.R);
-            stag[o] = F.R < 0 ? F.tag : 0;
-            sS[o] = F.S;
+            sface[o] = empty ? -1 : finv[k] * 2 + side;
+            snbr[o] = (empty || F.R < 0) ? -1 : (side ? F.L : F.R);
+            stag[o] = empty ? -1 : F.R < 0 ? F.tag : 0;
+            sS[o] = empty ? 0.0 : F.S;
+            /* an empty slot repeats the Gauss points of the cell's first face,
+             * an unused fourth point the face's first, so the positivity guard
+             * checks no other point */
             for (int d = 0; d < dim; ++d) {
-                sn[((size_t)d * ns + s) * n + i] = sg * F.n[d];
+                sn[((size_t)d * ns + s) * n + i] = empty ? 0.0 : sg * F.n[d];
                 for (int g = 0; g < ng; ++g)
                     sX[dim == 2 ? (((size_t)g * dim + d) * n + i) * ns + s : (((size_t)g * dim + d) * ns + s) * n + i] =
-                        (F.gp[g][d] - H.C[(size_t)i * dim + d]) * ih;
+                        (F.gp[g < F.ngp ? g : 0][d] - H.C[(size_t)i * dim + d]) * ih;
             }
         }
     }
@@ -335,6 +343,10 @@ int upload(cgks_ctx* c) {
     TRY(dalloc(c, &f.asave, n));
     TRY(dalloc(c, &f.poly, (size_t)(dim == 2 ? 40 : 80) * n));
     TRY(dalloc(c, &f.fX, (size_t)nf * ng * dim)); TRY(h2d(c, f.fX, fX));
+    if (c->hybrid) {
+        TRY(dalloc(c, &f.fw, (size_t)nf * ng));
+        TRY(h2d(c, f.fw, fw));
+    }
     TRY(dalloc(c, &f.fout, (size_t)nf * (2 * nv + 1)));
     TRY(dalloc(c, &f.R, (size_t)nv * n));
     TRY(dalloc(c, &f.gnew, (size_t)nv * dim * n));
@@ -1001,6 +1013,7 @@ int cgks_batch_create(int n, cgks_ctx* const* probs, cgks_batch** out) {
     for (int b = 0; b < n; ++b) {
         if (!probs[b] || !probs[b]->have_mesh) return CGKS_EINVAL;
         if (!same_shared_params(probs[0]->p, probs[b]->p)) return CGKS_EINVAL;
+        if (probs[b]->hybrid) return CGKS_EINVAL;   /* batches take simplex meshes */
     }
     cgks_batch* B = new cgks_batch();
     B->probs.assign(probs, probs + n);

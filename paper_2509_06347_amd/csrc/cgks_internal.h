@@ -25,8 +25,9 @@ struct HFace {
     double n[3];         /* unit normal L -> R */
     double S;            /* area (2-D: length) */
     double xc[3];        /* centre */
-    int ngp;
-    double gp[3][3];     /* Gauss points */
+    int ngp;             /* 2 (edge), 3 (triangle) or 4 (quadrilateral) */
+    double gp[4][3];     /* Gauss points */
+    double w[4];         /* their weights, summing to 1 */
 };
 
 struct HLevel {
@@ -42,7 +43,8 @@ struct HLevel {
     std::vector<int> color_off;           /* internal offsets of each colour, size ncolor+1 */
     int nslot = 0;                        /* max faces per cell */
     /* fine level only */
-    std::vector<int> nodes;
+    std::vector<int> nodes;               /* [n][dim+1]; mixed elements: flat, cell i from noff[i] */
+    std::vector<int> noff;                /* mixed elements: [n+1] */
     std::vector<double> h, mean0, op;     /* basis scale, basis means, LS operator (slot layout) */
     std::vector<int> nbasis;              /* per cell: quadratic, linear or constant basis */
 };
@@ -67,6 +69,7 @@ struct FineDev {
     double *Wsave, *gsave, *asave;    /* start-of-cycle copy for roll-back */
     double *poly;                     /* [n][40 | 80] per-cell polynomial record (reconstruction -> flux) */
     double *fX;                       /* [nf][ngp][dim] Gauss points of each face */
+    double *fw;                       /* mixed elements: [nf][4] Gauss weight x face area (0: unused point) */
     double *fout;                     /* [nf][2 nv + 1] per face: sum wS F, sum wS W(dt), DF product */
     double *R, *gnew, *anew, *dt, *dti;
     double *res;                      /* -R of the restriction evaluation */
@@ -139,6 +142,7 @@ struct cgks_ctx {
     hipStream_t own_stream = nullptr;     /* used when the caller sets no stream */
     std::string err;
     bool have_mesh = false;
+    bool hybrid = false;                  /* 3-D mixed-element (hybrid) mesh: 6 face slots, 4 Gauss points per face */
     std::vector<double> coords;
     std::vector<cgks::HLevel> hl;
     cgks::FineDev fine{};

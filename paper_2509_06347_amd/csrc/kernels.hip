@@ -97,12 +97,16 @@ __device__ __forceinline__ void fixed_factor_rhs(const KParams& kp, const Coarse
     for (int q = 0; q < NV; ++q) rhs[q] += (1.0 - kp.relax_beta) * (V / dti) * (double)dW[q * c.n + I];
 }
 
-template <int D>
+/* HY: 3-D hybrid meshes (tetrahedra, pyramids, prisms, hexahedra; Sec. 2.2):
+ * six face slots per cell (empty past the cell's faces) and four Gauss
+ * points per face (a triangle's fourth repeats its first with weight 0). */
+template <int D, bool HY = false>
 struct Shape {
+    static_assert(!HY || D == 3, "hybrid meshes are 3-D");
     static constexpr int NV = D + 2;
-    static constexpr int NS = D + 1;                /* faces per cell */
+    static constexpr int NS = HY ? 6 : D + 1;       /* face slots per cell */
     static constexpr int NQ = (D == 2) ? 5 : 9;     /* quadratic basis size */
-    static constexpr int NG = (D == 2) ? 2 : 3;     /* Gauss points per face */
+    static constexpr int NG = HY ? 4 : (D == 2) ? 2 : 3;   /* Gauss points per face */
     static constexpr int NC = NV * (1 + D);         /* state + gradient per Gauss point */
     static constexpr int NCOL = NS * (1 + D);       /* operator inputs */
     static constexpr int NK = NQ + D;               /* coefficients per component: p^2 part, Green-Gauss part */
@@ -178,9 +182,9 @@ __device__ __forceinline__ double beta_large(const double* a, const double* m) {
 /* Per-block LDS of the reconstruction: for each field, one double per cell of
  * the block (stride cells + 1, so that the record writes, which walk the
  * fields of one cell, spread over the banks). */
-template <int D>
+template <int D, bool HY>
 struct RLds {
-    using S = Shape<D>;
+    using S = Shape<D, HY>;
     static constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NK = S::NK;
     static constexpr int WN = 0;                     /* [NS][NV] neighbour averages (ghost states on boundary faces) */
     static constexpr int GN = WN + NS * NV;          /* [NS][NV][D] neighbour gradients, read by stage 2 */
@@ -223,11 +227,11 @@ struct RLds {
  * six waves per SIMD fit (80 VGPRs, asked for: 0.5 % faster per V-cycle than
  * five). */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
-template <int D, int CELLS>
-__global__ void __launch_bounds__(CELLS * (D + 1) * (D == 2 ? 2 : 3)) __attribute__((amdgpu_waves_per_eu(6)))
+template <int D, int CELLS, bool HY>
+__global__ void __launch_bounds__((CELLS * Shape<D, HY>::NS * Shape<D, HY>::NG)) __attribute__((amdgpu_waves_per_eu(HY ? 4 : 6)))
 k_recon(FineDev f, KParams kp0) {
-    using S = Shape<D>;
-    using L = RLds<D>;
+    using S = Shape<D, HY>;
+    using L = RLds<D, HY>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NCOL = S::NCOL, NK = S::NK;
     constexpr int cells = CELLS, nt = CELLS * NS * NG, cs = CELLS + 1;   /* compile-time: index math by shifts */
     static_assert(nt <= RTHREADS, "reconstruction block");
@@ -313,6 +317,11 @@ k_recon(FineDev f, KParams kp0) {
 #pragma unroll
         for (int d = 0; d < D; ++d) nout[d] = FLD(L::GEO + s * (1 + D) + 1 + d, cl);
         const int tag = f.slot_tag[s * n + i];
+        if (HY && tag < 0) {   /* empty slot (area 0): the cell's own averages keep its sums finite */
+#pragma unroll
+            for (int q = 0; q < NV; ++q) FLD(L::WN + s * NV + q, cl) = W0[q];
+            continue;
+        }
         if (tag == CGKS_TAG_SLIP) slip[cl] = 1;
         ghost_state<D, false>(kp, tag, W0, nullptr, nout, Wg, nullptr);
 #pragma unroll
@@ -533,10 +542,10 @@ __device__ __forceinline__ void eval_poly(const double* __restrict__ rec, const 
  * moments the kernel nearly fits two waves per SIMD, and asking for two
  * (a few registers spill) measured 1.6 % faster per V-cycle. */
 constexpr int FTHREADS = 256;
-template <int D, bool STATE>
+template <int D, bool STATE, bool HY>
 __global__ void __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(STATE ? 1 : 2)))
 k_flux(FineDev f, KParams kp0) {
-    using S = Shape<D>;
+    using S = Shape<D, HY>;
     constexpr int NV = S::NV, NG = S::NG, NPR = S::NPR, FO = S::FO, NS = S::NS;
     constexpr int FPW = 64 / NG;
     const int lane = threadIdx.x & 63;
@@ -569,7 +578,11 @@ k_flux(FineDev f, KParams kp0) {
         if (R >= 0) dt = fmin(dt, f.dt[R]);
         double Fk[NV], Gk[NV];
         gks_flux<D, STATE>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
-        const double ws = f.fS[fc] / NG;
+        double ws = f.fS[fc] / NG;
+        if constexpr (HY) {   /* per-point weight x area; a weight-0 point leaves the DF product alone */
+            ws = f.fw[(size_t)fc * NG + k];
+            if (ws == 0.0) a = 1.0;
+        }
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             F[q] = ws * Fk[q];
@@ -655,9 +668,9 @@ __device__ double update_fraction(const double* W, const double* dW, double kapp
     return 0.0;
 }
 
-template <int D>
+template <int D, bool HY>
 __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mode, double* partial, int* status) {
-    using S = Shape<D>;
+    using S = Shape<D, HY>;
     constexpr int NV = S::NV, NS = S::NS, NG = S::NG;
     const bool keep = (mode & FINE_KEEP) != 0;
     mode &= ~FINE_KEEP;
@@ -675,6 +688,7 @@ __global__ void __launch_bounds__(BLOCK) k_gather(FineDev f, KParams kp, int mod
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int sf = f.slot_face[s * n + i];
+            if (HY && sf < 0) continue;   /* empty slot */
             const int fc = sf >> 1;
             const double sg = (sf & 1) ? -1.0 : 1.0;
             double nn[D];
@@ -1308,54 +1322,58 @@ static inline int cblk(long m) { return (int)((m + CBLOCK - 1) / CBLOCK); }
 
 static inline int blocks(long m, int b) { return (int)((m + b - 1) / b); }
 
-template <int D>
+template <int D, bool HY>
 static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
     FineDev& f = c->fine;
     hipStream_t st = c->stream;
     if (which == 0) {
-        /* block = cells per block x faces x Gauss points */
-        using S = Shape<D>;
+        /* block = cells per block x faces x Gauss points (hybrid: 16 cells) */
+        using S = Shape<D, HY>;
         const int want = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
-        const int cells = want <= 16 ? 16 : (want <= 32 || D == 3 ? 32 : 64);
+        const int cells = (want <= 16 || HY) ? 16 : (want <= 32 || D == 3 ? 32 : 64);
         const dim3 grid(blocks(f.n, cells)), blk(cells * S::NS * S::NG);
-        const size_t lds = RLds<D>::bytes(cells);
-        if (cells == 16) k_recon<D, 16><<<grid, blk, lds, st>>>(f, c->kp);
-        else if (cells == 32) k_recon<D, 32><<<grid, blk, lds, st>>>(f, c->kp);
-        else k_recon<D, (D == 2 ? 64 : 32)><<<grid, blk, lds, st>>>(f, c->kp);
+        const size_t lds = RLds<D, HY>::bytes(cells);
+        if constexpr (HY) {
+            k_recon<D, 16, true><<<grid, blk, lds, st>>>(f, c->kp);
+        } else {
+            if (cells == 16) k_recon<D, 16, false><<<grid, blk, lds, st>>>(f, c->kp);
+            else if (cells == 32) k_recon<D, 32, false><<<grid, blk, lds, st>>>(f, c->kp);
+            else k_recon<D, (D == 2 ? 64 : 32), false><<<grid, blk, lds, st>>>(f, c->kp);
+        }
     } else if (which == 1) {
         /* 64 / NG faces per wave */
+        constexpr int FPW = 64 / Shape<D, HY>::NG;
         const int b = block ? block : c->blk_flux;
-        const long waves = ((long)f.nf + 64 / Shape<D>::NG - 1) / (64 / Shape<D>::NG);
+        const long waves = ((long)f.nf + FPW - 1) / FPW;
         /* the residual for restriction uses no slopes (the state at t = dt);
          * inviscid, its flux needs none of their moments */
         const bool lite = (mode & ~FINE_KEEP) == FINE_RESTRICT && !(c->kp.reynolds > 0.0) && !f.pid;
-        if (lite) k_flux<D, false><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
-        else k_flux<D, true><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        if (lite) k_flux<D, false, HY><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        else k_flux<D, true, HY><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
     } else {
         /* the norm partials use a fixed 256-thread block */
         const int m = mode & ~FINE_KEEP;
         const int b = (m == FINE_STEP_NORM && !f.pid) ? BLOCK : (block ? block : c->blk_gather);
-        k_gather<D><<<blocks(f.n, b), b, 0, st>>>(f, c->kp, mode, c->ws.partial, c->ws.status);
+        k_gather<D, HY><<<blocks(f.n, b), b, 0, st>>>(f, c->kp, mode, c->ws.partial, c->ws.status);
     }
 }
 
-void launch_fine_recon(cgks_ctx* c) {
-    if (c->dim == 2) fine_kernel<2>(c, 0, 0, FINE_EVAL);
-    else fine_kernel<3>(c, 0, 0, FINE_EVAL);
+static void fine_kernel_any(cgks_ctx* c, int which, int block, int mode) {
+    if (c->dim == 2) fine_kernel<2, false>(c, which, block, mode);
+    else if (c->hybrid) fine_kernel<3, true>(c, which, block, mode);
+    else fine_kernel<3, false>(c, which, block, mode);
 }
 
-void launch_fine_kernel(cgks_ctx* c, int which, int block) {
-    if (c->dim == 2) fine_kernel<2>(c, which, block, FINE_EVAL);
-    else fine_kernel<3>(c, which, block, FINE_EVAL);
-}
+void launch_fine_recon(cgks_ctx* c) { fine_kernel_any(c, 0, 0, FINE_EVAL); }
 
-template <int D>
+void launch_fine_kernel(cgks_ctx* c, int which, int block) { fine_kernel_any(c, which, block, FINE_EVAL); }
+
 static void fine_residual(cgks_ctx* c, int mode) {
     FineDev& f = c->fine;
     hipStream_t st = c->stream;
-    fine_kernel<D>(c, 0, 0, mode);
-    fine_kernel<D>(c, 1, 0, mode);
-    fine_kernel<D>(c, 2, 0, mode);
+    fine_kernel_any(c, 0, 0, mode);
+    fine_kernel_any(c, 1, 0, mode);
+    fine_kernel_any(c, 2, 0, mode);
     if ((mode & ~FINE_KEEP) == FINE_STEP_NORM) {
         if (f.pid) {
             k_norm_batch<<<c->ws.nprob, BLOCK, 0, st>>>(f.r2, c->ws.poff, c->ws.ptab, c->ws.history,
@@ -1368,10 +1386,7 @@ static void fine_residual(cgks_ctx* c, int mode) {
     }
 }
 
-void launch_fine_residual(cgks_ctx* c, int mode) {
-    if (c->dim == 2) fine_residual<2>(c, mode);
-    else fine_residual<3>(c, mode);
-}
+void launch_fine_residual(cgks_ctx* c, int mode) { fine_residual(c, mode); }
 
 template <int D, class T>
 static void coarse_rhs(cgks_ctx* c, CoarseDev& L, int mode) {

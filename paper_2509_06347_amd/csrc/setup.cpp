@@ -32,28 +32,50 @@ int hip_fail(cgks_ctx* c, hipError_t e, const char* what) {
 namespace {
 
 struct FaceKey {
-    int v[3];
-    bool operator==(const FaceKey& o) const { return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2]; }
+    int v[4];            /* sorted node ids; -1 past the face's node count */
+    bool operator==(const FaceKey& o) const {
+        return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2] && v[3] == o.v[3];
+    }
     bool operator<(const FaceKey& o) const {
-        if (v[0] != o.v[0]) return v[0] < o.v[0];
-        if (v[1] != o.v[1]) return v[1] < o.v[1];
-        return v[2] < o.v[2];
+        for (int i = 0; i < 4; ++i)
+            if (v[i] != o.v[i]) return v[i] < o.v[i];
+        return false;
     }
 };
 struct FaceKeyHash {
     size_t operator()(const FaceKey& k) const {
         uint64_t h = 1469598103934665603ull;
-        for (int i = 0; i < 3; ++i) h = (h ^ (uint64_t)(uint32_t)k.v[i]) * 1099511628211ull;
+        for (int i = 0; i < 4; ++i) h = (h ^ (uint64_t)(uint32_t)k.v[i]) * 1099511628211ull;
         return (size_t)h;
     }
 };
 
 FaceKey make_key(const int* ids, int cnt) {
     FaceKey k;
-    k.v[0] = k.v[1] = k.v[2] = -1;
+    k.v[0] = k.v[1] = k.v[2] = k.v[3] = -1;
     for (int i = 0; i < cnt; ++i) k.v[i] = ids[i];
     std::sort(k.v, k.v + cnt);
     return k;
+}
+
+/* Faces of the 3-D element types of the mixed input (Sec. 2.2), each as a
+ * cycle of the element's local nodes: a tetrahedron's face t leaves out
+ * node t; a pyramid lists its base and then its four triangles; a prism its
+ * two triangles and then its three quadrilaterals; a hexahedron its first
+ * and last quadrilaterals and then the four sides. */
+struct ElemTable {
+    int nface;
+    int cnt[6];
+    int node[6][4];
+};
+
+const ElemTable* element(int nnode) {
+    static const ElemTable T4 = {4, {3, 3, 3, 3}, {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}}};
+    static const ElemTable T5 = {5, {4, 3, 3, 3, 3}, {{0, 1, 2, 3}, {0, 1, 4}, {1, 2, 4}, {2, 3, 4}, {3, 0, 4}}};
+    static const ElemTable T6 = {5, {3, 3, 4, 4, 4}, {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}}};
+    static const ElemTable T8 = {6, {4, 4, 4, 4, 4, 4},
+                                 {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}}};
+    return nnode == 4 ? &T4 : nnode == 5 ? &T5 : nnode == 6 ? &T6 : nnode == 8 ? &T8 : nullptr;
 }
 
 /* Basis of the quadratic reconstruction: scaled monomials ((x-xc)/h)^e. */
@@ -223,20 +245,125 @@ void cell_vertices(const cgks_ctx* c, const HLevel& L, int i, double* P) {
         for (int d = 0; d < dim; ++d) P[j * dim + d] = c->coords[(size_t)L.nodes[i * (dim + 1) + j] * dim + d];
 }
 
+/* A mixed element with planar faces as tetrahedra: the mean of its nodes
+ * joined to a fan of triangles on each face (a quadrilateral's fan starts at
+ * its first node).  fn(P, vol) gets the 4 x 3 vertices and the volume of
+ * each. */
+template <class Fn>
+void for_each_cone(const cgks_ctx* c, const HLevel& L, int i, Fn fn) {
+    const int off = L.noff[i], cnt = L.noff[i + 1] - off;
+    const ElemTable* et = element(cnt);
+    const double* X = c->coords.data();
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < cnt; ++j)
+        for (int d = 0; d < 3; ++d) m[d] += X[(size_t)L.nodes[off + j] * 3 + d];
+    for (int d = 0; d < 3; ++d) m[d] /= cnt;
+    for (int fc = 0; fc < et->nface; ++fc)
+        for (int t = 1; t + 1 < et->cnt[fc]; ++t) {
+            double P[12];
+            const int ids[3] = {et->node[fc][0], et->node[fc][t], et->node[fc][t + 1]};
+            for (int d = 0; d < 3; ++d) {
+                P[d] = m[d];
+                for (int v = 0; v < 3; ++v) P[3 * (v + 1) + d] = X[(size_t)L.nodes[off + ids[v]] * 3 + d];
+            }
+            double e[3][3];
+            for (int v = 0; v < 3; ++v)
+                for (int d = 0; d < 3; ++d) e[v][d] = P[3 * (v + 1) + d] - P[d];
+            const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                               e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                               e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+            fn(P, std::fabs(det) / 6.0);
+        }
+}
+
+/* Cell average of f over fine cell i (exact for quadratics). */
+template <class Fn>
+double cell_average(const cgks_ctx* c, const HLevel& L, int i, Fn f) {
+    if (!c->hybrid) {
+        double P[12];
+        cell_vertices(c, L, i, P);
+        return simplex_average(c->dim, P, f);
+    }
+    double acc = 0.0, vol = 0.0;
+    for_each_cone(c, L, i, [&](const double* P, double v) {
+        acc += v * simplex_average(3, P, f);
+        vol += v;
+    });
+    return acc / vol;
+}
+
+/* Planar quadrilateral face with node cycle x0..x3: area vector
+ * (x2 - x0) x (x3 - x1) / 2, centre from the triangles (x0, x1, x2) and
+ * (x0, x2, x3), and the 2 x 2 Gauss points of the bilinear map from
+ * [-1, 1]^2 with weights proportional to the map's area element.  False when
+ * x3 is off the plane of the others. */
+bool quad_face(const double* const* x, HFace& F) {
+    auto cr = [](const double* a, const double* b, double* o) {
+        o[0] = a[1] * b[2] - a[2] * b[1];
+        o[1] = a[2] * b[0] - a[0] * b[2];
+        o[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    auto len = [](const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); };
+    double d02[3], d13[3], A[3];
+    for (int d = 0; d < 3; ++d) {
+        d02[d] = x[2][d] - x[0][d];
+        d13[d] = x[3][d] - x[1][d];
+    }
+    cr(d02, d13, A);
+    const double la = len(A);
+    F.S = 0.5 * la;
+    for (int d = 0; d < 3; ++d) F.n[d] = A[d] / la;
+    double h = 0.0;
+    for (int d = 0; d < 3; ++d) h += F.n[d] * (x[3][d] - x[0][d]);
+    if (std::fabs(h) > 1e-9 * std::sqrt(F.S)) return false;
+    double e1[3], e3[3], t1[3], t2[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = x[1][d] - x[0][d];
+        e3[d] = x[3][d] - x[0][d];
+    }
+    cr(e1, d02, t1);
+    cr(d02, e3, t2);
+    const double a1 = len(t1), a2 = len(t2);
+    for (int d = 0; d < 3; ++d)
+        F.xc[d] = (a1 * (x[0][d] + x[1][d] + x[2][d]) + a2 * (x[0][d] + x[2][d] + x[3][d])) / (3.0 * (a1 + a2));
+    F.ngp = 4;
+    const double r = 1.0 / std::sqrt(3.0);
+    const double su[4] = {-r, r, r, -r}, sv[4] = {-r, -r, r, r};
+    double jw[4], jt = 0.0;
+    for (int g = 0; g < 4; ++g) {
+        const double N[4] = {(1 - su[g]) * (1 - sv[g]), (1 + su[g]) * (1 - sv[g]), (1 + su[g]) * (1 + sv[g]),
+                             (1 - su[g]) * (1 + sv[g])};
+        const double Nu[4] = {-(1 - sv[g]), 1 - sv[g], 1 + sv[g], -(1 + sv[g])};
+        const double Nv[4] = {-(1 - su[g]), -(1 + su[g]), 1 + su[g], 1 - su[g]};
+        double xu[3] = {0, 0, 0}, xv[3] = {0, 0, 0}, J[3];
+        for (int d = 0; d < 3; ++d) {
+            double p = 0.0;
+            for (int k = 0; k < 4; ++k) {
+                p += N[k] * x[k][d];
+                xu[d] += Nu[k] * x[k][d];
+                xv[d] += Nv[k] * x[k][d];
+            }
+            F.gp[g][d] = 0.25 * p;
+        }
+        cr(xu, xv, J);
+        jw[g] = len(J);
+        jt += jw[g];
+    }
+    for (int g = 0; g < 4; ++g) F.w[g] = jw[g] / jt;
+    return true;
+}
+
 /* Reconstruction operator of fine cell i in slot layout: column
  * s*(1+dim)+0 multiplies (Q_nbr(s) - Q_i), column s*(1+dim)+1+d the
  * neighbour's slope d; empty slots (boundary faces) have zero columns. */
 void build_operator(cgks_ctx* c, int i) {
     const int dim = c->dim;
     HLevel& L = c->hl[0];
-    const int nq = (dim == 2) ? 5 : 9, nslot = dim + 1, ncol = nslot * (1 + dim);
+    const int nq = (dim == 2) ? 5 : 9, nslot = (int)L.cf[i].size(), ncol = L.nslot * (1 + dim);
     const double* xc = &L.C[i * dim];
     const double h = L.h[i];
-    double P0[12];
-    cell_vertices(c, L, i, P0);
     for (int k = 0; k < nq; ++k)
-        L.mean0[(size_t)k * L.n + i] =
-            simplex_average(dim, P0, [&](const double* x) { return mono(dim, k, x, xc, h); });
+        L.mean0[(size_t)k * L.n + i] = cell_average(c, L, i, [&](const double* x) { return mono(dim, k, x, xc, h); });
     std::vector<int> slots, nbrs;
     for (int s = 0; s < nslot; ++s) {
         const HFace& f = L.faces[L.cf[i][s]];
@@ -254,14 +381,12 @@ void build_operator(cgks_ctx* c, int i) {
         std::vector<double> w(nn);
         for (int m = 0; m < nn; ++m) {
             int j = nbrs[m];
-            double Pj[12];
-            cell_vertices(c, L, j, Pj);
             const double* xj = &L.C[j * dim];
             double r2 = 0.0;
             for (int d = 0; d < dim; ++d) r2 += (xj[d] - xc[d]) * (xj[d] - xc[d]);
             w[m] = std::sqrt(r2);
             for (int k = 0; k < nb; ++k) {
-                double avg = simplex_average(dim, Pj, [&](const double* x) { return mono(dim, k, x, xc, h); });
+                double avg = cell_average(c, L, j, [&](const double* x) { return mono(dim, k, x, xc, h); });
                 E[m * nb + k] = avg - L.mean0[(size_t)k * L.n + i];
                 for (int d = 0; d < dim; ++d) A[(m * dim + d) * nb + k] = w[m] * mono_dx(dim, k, d, xj, xc, h);
             }
@@ -482,20 +607,44 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
     if (n_levels < 1 || n_levels > 8) return fail(c, CGKS_EINVAL, "n_levels out of range");
     if (m->n_cells <= 0 || m->n_nodes <= 0 || !m->coords || !m->cell_nodes)
         return fail(c, CGKS_EINVAL, "empty mesh");
+    const bool mixed = m->cell_offsets != nullptr;
+    if (mixed != (m->bface_offsets != nullptr))
+        return fail(c, CGKS_EINVAL, "cell_offsets and bface_offsets must be given together");
+    if (mixed && dim != 3) return fail(c, CGKS_EINVAL, "mixed elements are 3-D only");
+    c->hybrid = mixed;
     c->coords.assign(m->coords, m->coords + (size_t)m->n_nodes * dim);
     c->hl.assign(n_levels, HLevel());
     HLevel& L = c->hl[0];
     L.n = m->n_cells;
-    L.nodes.assign(m->cell_nodes, m->cell_nodes + (size_t)L.n * (dim + 1));
+    if (mixed) {
+        L.noff.assign(m->cell_offsets, m->cell_offsets + L.n + 1);
+        if (L.noff[0] != 0) return fail(c, CGKS_EMESH, "cell_offsets[0] is not 0");
+        for (int i = 0; i < L.n; ++i)
+            if (!element(L.noff[i + 1] - L.noff[i]))
+                return fail(c, CGKS_EMESH, "cell " + std::to_string(i) + ": node count other than 4, 5, 6 or 8");
+        L.nodes.assign(m->cell_nodes, m->cell_nodes + L.noff[L.n]);
+    } else {
+        L.nodes.assign(m->cell_nodes, m->cell_nodes + (size_t)L.n * (dim + 1));
+    }
     L.V.resize(L.n);
     L.C.resize((size_t)L.n * dim);
     L.h.resize(L.n);
     const double* X = c->coords.data();
     for (int i = 0; i < L.n; ++i) {
-        const int* v = &L.nodes[(size_t)i * (dim + 1)];
-        for (int j = 0; j <= dim; ++j)
+        const int* v = mixed ? &L.nodes[L.noff[i]] : &L.nodes[(size_t)i * (dim + 1)];
+        const int nv = mixed ? L.noff[i + 1] - L.noff[i] : dim + 1;
+        for (int j = 0; j < nv; ++j)
             if (v[j] < 0 || v[j] >= m->n_nodes) return fail(c, CGKS_EMESH, "cell node out of range");
-        if (dim == 2) {
+        if (mixed) {
+            double vol = 0.0, mom[3] = {0.0, 0.0, 0.0};
+            for_each_cone(c, L, i, [&](const double* P, double cv) {
+                vol += cv;
+                for (int d = 0; d < 3; ++d) mom[d] += cv * (((P[d] + P[3 + d]) + P[6 + d]) + P[9 + d]) / 4.0;
+            });
+            L.V[i] = vol;
+            for (int d = 0; d < 3; ++d) L.C[i * 3 + d] = mom[d] / vol;
+            L.h[i] = std::cbrt(vol);
+        } else if (dim == 2) {
             const double *a = X + 2 * v[0], *b = X + 2 * v[1], *e = X + 2 * v[2];
             L.V[i] = 0.5 * ((b[0] - a[0]) * (e[1] - a[1]) - (e[0] - a[0]) * (b[1] - a[1]));
             for (int d = 0; d < 2; ++d) L.C[i * 2 + d] = ((a[d] + b[d]) + e[d]) / 3.0;
@@ -523,12 +672,26 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
     std::vector<std::array<int, 2>> cells;
     std::vector<int> cnt;
     std::vector<std::array<int, 2>> cellslot;
-    for (int i = 0; i < L.n; ++i)
-        for (int k = 0; k <= dim; ++k) {
-            int ids[3], t = 0;
+    /* node ids of local face k of cell i, in the element's cycle */
+    auto face_nodes = [&](int i, int k, int* ids) {
+        if (!mixed) {
+            int t = 0;
             for (int j = 0; j <= dim; ++j)
                 if (j != k) ids[t++] = L.nodes[(size_t)i * (dim + 1) + j];
-            FaceKey key = make_key(ids, dim);
+            return dim;
+        }
+        const ElemTable* et = element(L.noff[i + 1] - L.noff[i]);
+        for (int j = 0; j < et->cnt[k]; ++j) ids[j] = L.nodes[L.noff[i] + et->node[k][j]];
+        return et->cnt[k];
+    };
+    L.cf.assign(L.n, {});
+    for (int i = 0; i < L.n; ++i) {
+        const int nfc = mixed ? element(L.noff[i + 1] - L.noff[i])->nface : dim + 1;
+        L.cf[i].assign(nfc, -1);
+        for (int k = 0; k < nfc; ++k) {
+            int ids[4];
+            const int cnt_k = face_nodes(i, k, ids);
+            FaceKey key = make_key(ids, cnt_k);
             auto it = fmap.find(key);
             if (it == fmap.end()) {
                 fmap.emplace(key, (int)keys.size());
@@ -544,16 +707,19 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
                 cnt[f] = 2;
             }
         }
+    }
     std::vector<int> order(keys.size());
     for (size_t f = 0; f < keys.size(); ++f) order[f] = (int)f;
     std::sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
     std::unordered_map<FaceKey, int, FaceKeyHash> btag;
     for (int b = 0; b < m->n_bfaces; ++b) {
-        FaceKey key = make_key(m->bface_nodes + (size_t)b * dim, dim);
+        const int b0 = mixed ? m->bface_offsets[b] : b * dim;
+        const int bc = mixed ? m->bface_offsets[b + 1] - b0 : dim;
+        if (bc < dim || bc > 4) return fail(c, CGKS_EMESH, "boundary face with a bad node count");
+        FaceKey key = make_key(m->bface_nodes + b0, bc);
         btag[key] = m->bface_tag[b];
     }
     L.faces.resize(keys.size());
-    L.cf.assign(L.n, std::vector<int>(dim + 1, -1));
     int nmatched = 0;
     for (size_t o = 0; o < order.size(); ++o) {
         const int f = order[o];
@@ -577,7 +743,14 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
         if (c1 >= 0) L.cf[c1][cellslot[f][1]] = (int)o;
         const int* k = keys[f].v;
         const double* CL = &L.C[(size_t)F.L * dim];
-        if (dim == 2) {
+        int cyc[4];
+        const int ncyc = face_nodes(c0, cellslot[f][0], cyc);
+        if (mixed) k = cyc;   /* Gauss points in the order of the first cell's cycle */
+        for (int g = 0; g < 4; ++g) F.w[g] = 0.0;
+        if (mixed && ncyc == 4) {
+            const double* x[4] = {X + 3 * cyc[0], X + 3 * cyc[1], X + 3 * cyc[2], X + 3 * cyc[3]};
+            if (!quad_face(x, F)) return fail(c, CGKS_EMESH, "non-planar quadrilateral face");
+        } else if (dim == 2) {
             const double *a = X + 2 * k[0], *b = X + 2 * k[1];
             const double dx = b[0] - a[0], dy = b[1] - a[1];
             F.S = std::sqrt(dx * dx + dy * dy);
@@ -586,6 +759,7 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
             F.xc[0] = 0.5 * (a[0] + b[0]);
             F.xc[1] = 0.5 * (a[1] + b[1]);
             F.ngp = 2;
+            F.w[0] = F.w[1] = 0.5;
             const double t[2] = {0.5 - std::sqrt(3.0) / 6.0, 0.5 + std::sqrt(3.0) / 6.0};
             for (int g = 0; g < 2; ++g) {
                 F.gp[g][0] = a[0] + t[g] * dx;
@@ -608,6 +782,7 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
                 F.xc[d] = ((a[d] + b[d]) + e[d]) / 3.0;
             }
             F.ngp = 3;
+            F.w[0] = F.w[1] = F.w[2] = 1.0 / 3.0;
             const double hi = 2.0 / 3.0, lo = 1.0 / 6.0;
             for (int g = 0; g < 3; ++g)
                 for (int d = 0; d < 3; ++d)
@@ -619,7 +794,7 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
             for (int d = 0; d < dim; ++d) F.n[d] = -F.n[d];
     }
     if (nmatched != m->n_bfaces) return fail(c, CGKS_EMESH, "a tagged boundary face is not on the boundary");
-    L.nslot = dim + 1;
+    L.nslot = mixed ? 6 : dim + 1;
     /* Coarse levels from parent maps (or Alg. 3). */
     for (int l = 1; l < n_levels; ++l) {
         HLevel& F = c->hl[l - 1];
@@ -668,7 +843,7 @@ int setup_host(cgks_ctx* c, const cgks_mesh* m, int n_levels, const int32_t* con
     /* Reconstruction operators of the fine level. */
     const int nq = (dim == 2) ? 5 : 9;
     L.mean0.assign((size_t)nq * L.n, 0.0);
-    L.op.assign((size_t)nq * (dim + 1) * (1 + dim) * L.n, 0.0);
+    L.op.assign((size_t)nq * L.nslot * (1 + dim) * L.n, 0.0);
     L.nbasis.assign(L.n, 0);
     for (int i = 0; i < L.n; ++i) build_operator(c, i);
     return CGKS_OK;

@@ -1,0 +1,132 @@
+"""GPU (HIP) vs CPU oracle parity on 3-D hybrid meshes (Sec. 2.2: tetrahedra,
+pyramids, prisms and hexahedra with 4, 5, 5 and 6 faces, triangular faces
+with the 3-point rule and quadrilateral faces with the 2 x 2 Gauss rule).
+
+Meshes: synthmesh.hybrid_box, a graded, frustum-mapped box of 8^3 cubes cut
+into all four element types (planar faces; the faces of constant x or y are
+trapezoids), far field on five sides and a wall on z = 0; levels are the
+cubes and their 2 x 2 x 2 blocks, or Alg. 3 agglomerates.  Bars as on
+tetrahedra: fine residual within 1e-12 of its largest entry, three V-cycles
+within 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synthmesh as sm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2509_06347_amd import cgks
+    return cgks
+
+
+CASES = {
+    "euler_hybrid": (lambda: sm.hybrid_box(8, seed=1, tags={"z0": sm.SLIP}),
+                     dict(dim=3, mach=0.5, aoa_deg=10.0)),
+    "ns_hybrid_adiabatic": (lambda: sm.hybrid_box(8, seed=2, tags={"z0": sm.ADIABATIC}),
+                            dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
+    "ns_hybrid_isothermal": (lambda: sm.hybrid_box(8, seed=3, tags={"z0": sm.ISOTHERMAL}),
+                             dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
+}
+
+
+def _pair(cg, orc, mesh, n_levels=3, use_parents=True, **params):
+    print(f"[case] hybrid cells={mesh.n_cells} {mesh.info} parents={use_parents} params={params}", flush=True)
+    return (cg.Solver(mesh, n_levels=n_levels, use_parents=use_parents, **params),
+            orc.Oracle(mesh, n_levels=n_levels, use_parents=use_parents, **params))
+
+
+def _perturbed(mesh, o, mach, seed, amp=0.03, slope=2e-3):
+    """Smooth perturbed free stream, the velocity ramped to zero at the wall."""
+    V, C = o.cell_geometry(0)
+    rng = np.random.default_rng(seed)
+    x, y, z = C[:, 0], C[:, 1], C[:, 2]
+    ramp = np.tanh(z / 0.2)
+    a = np.radians(10.0)
+    rho = 1.0 + amp * np.sin(3.0 * x) * np.cos(2.0 * y + z)
+    u = mach * np.cos(a) * (1.0 + amp * np.cos(2.5 * z)) * ramp
+    v = mach * np.sin(a) * ramp + mach * amp * np.sin(2.0 * x)
+    w = mach * amp * np.sin(3.0 * y) * z
+    p = (1.0 + amp * np.cos(2.0 * x + 1.5 * y - z)) / 1.4
+    W = np.stack([rho, rho * u, rho * v, rho * w, p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)], axis=1)
+    grad = slope * rng.standard_normal((mesh.n_cells, 5, 3))
+    alpha = rng.uniform(0.5, 1.0, mesh.n_cells)
+    return W, grad, alpha
+
+
+@pytest.mark.parametrize("use_parents", [True, False])
+def test_setup_parity_hybrid(cg, orc, use_parents):
+    mesh, params = CASES["euler_hybrid"][0](), CASES["euler_hybrid"][1]
+    for k in ("tets", "pyramids", "prisms", "hexahedra"):
+        assert mesh.info[k] > 0
+    g, o = _pair(cg, orc, mesh, use_parents=use_parents, **params)
+    assert g.sizes == [tuple(s) for s in o.sizes]
+    for l in range(3):
+        cgc, ncg = g.coloring(l)
+        coc, nco = o.coloring(l)
+        assert ncg == nco and np.array_equal(cgc, coc)
+        Vg, Cg = g.cell_geometry(l)
+        Vo, Co = o.cell_geometry(l)
+        np.testing.assert_allclose(Vg, Vo, rtol=1e-13)
+        np.testing.assert_allclose(Cg, Co, rtol=1e-13, atol=1e-14)
+
+
+def test_free_stream_preserved_hybrid(cg):
+    mesh, params = CASES["euler_hybrid"][0](), CASES["euler_hybrid"][1]
+    g = cg.Solver(mesh, n_levels=3, **params)
+    g.init_freestream()
+    R, grad, a = g.residual(0)
+    assert np.abs(R).max() <= 1e-13
+    assert np.abs(grad).max() <= 1e-12 and np.all(a == 1.0)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fine_residual_parity_hybrid(cg, orc, case):
+    mesh, params = CASES[case][0](), CASES[case][1]
+    g, o = _pair(cg, orc, mesh, **params)
+    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=5)
+    for s in (g, o):
+        s.set_state(W, grad, alpha)
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    scale = np.abs(Ro).max()
+    print(f"residual: max |dR| / max |R| = {np.abs(Rg - Ro).max() / scale:.2e}", flush=True)
+    assert np.abs(Rg - Ro).max() <= 1e-12 * scale
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    np.testing.assert_allclose(ag, ao, rtol=1e-12, atol=1e-13)
+    dg, ig = g.time_steps(0)
+    do, io = o.time_steps(0)
+    np.testing.assert_allclose(dg, do, rtol=1e-13)
+    np.testing.assert_allclose(ig, io, rtol=1e-13)
+
+
+@pytest.mark.parametrize("case,use_parents", [("euler_hybrid", True), ("ns_hybrid_adiabatic", True),
+                                              ("ns_hybrid_isothermal", False)])
+def test_vcycle_trajectory_parity_hybrid(cg, orc, case, use_parents):
+    mesh, params = CASES[case][0](), CASES[case][1]
+    g, o = _pair(cg, orc, mesh, use_parents=use_parents, **params)
+    W, grad, alpha = _perturbed(mesh, o, params["mach"], seed=7, slope=0.0)
+    for s in (g, o):
+        s.set_state(W, None, None)
+    ng = g.run_cycles(3)
+    no = np.array([o.vcycle() for _ in range(3)])
+    print(f"norms gpu {ng} oracle {no}", flush=True)
+    np.testing.assert_allclose(ng, no, rtol=1e-10)
+    Wg, gg, ag = g.get_state()
+    Wo, go, ao = o.get_state()
+    assert np.abs(Wg - Wo).max() <= 1e-10 * np.abs(Wo).max()
+    assert np.abs(gg - go).max() <= 1e-9 * max(np.abs(go).max(), 1e-12)
+    np.testing.assert_allclose(ag, ao, rtol=1e-10, atol=1e-12)
+
+
+def test_hybrid_mesh_is_refused_by_batches(cg):
+    mesh, params = CASES["euler_hybrid"][0](), CASES["euler_hybrid"][1]
+    s = cg.Solver(mesh, n_levels=3, **params)
+    with pytest.raises(cg.CgksError):
+        cg.Batch([s])
