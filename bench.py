@@ -8,7 +8,9 @@ geometric radial stretching 1.2, refined twice by Freudenthal subdivision ->
 nested levels (393,216 and 49,152 agglomerates), slip wall, far field.  The
 cycles start impulsively from the free stream with a 10-cycle implicit-CFL
 ramp.  `--workload cylinder_ns_mach8_131k` runs the 2-D viscous Mach 8
-cylinder (131,072 triangles) instead.
+cylinder (131,072 triangles) instead, `--workload hybrid_box_ns_mach0.5_1.2M`
+a viscous box of 1,201,412 hybrid cells (tetrahedra, pyramids, prisms and
+hexahedra; isothermal wall at z = 0).
 
 A "step" is one full 3-level V-cycle (fine residual, explicit fine step,
 second fine residual, restriction, 6 multi-colour LU-SGS iterations on each
@@ -55,6 +57,9 @@ MI355X_BF16_MFMA_TFLOPS = 2500.0   # dense
 RECON_BYTES_PER_CELL = {
     3: 8 * (5 + 15 + 1 + 1 + 1 + 4 + 12 + 9 + 144 + 36) + 4 * 8 + 8 * (5 * 12 + 2),
     2: 8 * (4 + 8 + 3 + 3 + 6 + 5 + 45 + 12) + 4 * 6 + 8 * (4 * 7 + 2),
+    # hybrid cells: 6 face slots (areas 6, normals 18, operator 9 x 24, Gauss
+    # offsets 4 x 3 x 6, neighbour ids and tags 12 int32)
+    "3h": 8 * (5 + 15 + 1 + 1 + 1 + 6 + 18 + 9 + 216 + 72) + 4 * 12 + 8 * (5 * 12 + 2),
 }
 
 # HBM bytes moved by one launch of a kernel on a workload, from rocprofv3
@@ -62,8 +67,10 @@ RECON_BYTES_PER_CELL = {
 # counter's reading for a plain device copy of known size.  Valid only for the
 # kernel source the counters were taken with; absent (null) otherwise.
 TRAFFIC_BYTES = {
-    # FETCH_SIZE 3,938,100 KiB x 2.0 + WRITE_SIZE 1,983,700 KiB x 1.0, median per launch
-    ("sphere_euler_mach6_3.1M", "k_recon<3, 16>"): (3.9381e6 * 2.0 + 1.9837e6 * 1.0) * 1024,
+    # FETCH_SIZE 3,938,054 KiB x 2.0 + WRITE_SIZE 1,983,744 KiB x 1.0, median per launch
+    ("sphere_euler_mach6_3.1M", "k_recon<3, 16, false>"): (3.938054e6 * 2.0 + 1.983744e6 * 1.0) * 1024,
+    # FETCH_SIZE 3,494,185 KiB x 2.0 + WRITE_SIZE 769,655 KiB x 1.0
+    ("hybrid_box_ns_mach0.5_1.2M", "k_recon<3, 16, true>"): (3.494185e6 * 2.0 + 0.769655e6 * 1.0) * 1024,
 }
 
 # FP64 operations the flux kernel executes per face Gauss point, from the
@@ -72,7 +79,9 @@ TRAFFIC_BYTES = {
 # Valid only for the flux source the counters were taken with.
 FLUX_FP64_OPS_PER_POINT = {
     # 64 x (ADD 8.7139e7 + MUL 2.2698e8 + 2 FMA 5.9897e8 + TRANS 1.3662e7) / 18,627,840 points
-    ("sphere_euler_mach6_3.1M", "k_flux<3, true>"): 5242,
+    ("sphere_euler_mach6_3.1M", "k_flux<3, true, false>"): 5242,
+    # 64 x (ADD 6.1384e7 + MUL 1.5297e8 + 2 FMA 4.0608e8 + TRANS 9.906e6) / 12,278,676 Gauss-point lanes
+    ("hybrid_box_ns_mach0.5_1.2M", "k_flux<3, true, true>"): 5402,
 }
 
 
@@ -84,6 +93,11 @@ def workload(name):
         return sm.sphere_shell_kuhn(8, 4, 4, nref=2), dict(mach=6.0, cfl_ramp=10)
     if name == "cylinder_ns_mach8_131k":
         return sm.cylinder_ns_large(), dict(mach=8.0, reynolds=1e4, prandtl=0.72, wall_T_ratio=1.0)
+    if name == "hybrid_box_ns_mach0.5_1.2M":
+        # 80^3 cubes as 178,284 tetrahedra, 445,710 pyramids, 309,120 prisms and
+        # 268,298 hexahedra; isothermal no-slip wall at z = 0, far field elsewhere
+        return (sm.hybrid_box(80, seed=11, tags={"z0": sm.ISOTHERMAL}),
+                dict(mach=0.5, aoa_deg=10.0, reynolds=1e4, prandtl=0.72, wall_T_ratio=1.0, cfl_ramp=10))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -94,10 +108,13 @@ def initial_state(solver, mesh, params):
     W, _, _ = solver.get_state()
     if params.get("reynolds", 0.0) > 0.0:
         V, C = solver.cell_geometry(0)
-        r = np.tanh((np.hypot(C[:, 0], C[:, 1]) - 0.5) / 0.3)
-        W[:, 1] *= r
-        W[:, 2] *= r
-        W[:, 3] = (1.0 / 1.4) / 0.4 + 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0]
+        if mesh.info.get("kind") == "hybrid_box":       # wall at z = 0
+            r = np.tanh(C[:, 2] / 0.1)
+        else:                                           # cylinder of radius 0.5
+            r = np.tanh((np.hypot(C[:, 0], C[:, 1]) - 0.5) / 0.3)
+        d = mesh.dim
+        W[:, 1:1 + d] *= r[:, None]
+        W[:, d + 1] = (1.0 / 1.4) / 0.4 + 0.5 * (W[:, 1:1 + d] ** 2).sum(axis=1) / W[:, 0]
         solver.set_state(W)
     return W
 
@@ -541,16 +558,18 @@ def main():
         kern[name] = {"avg_ms": avg, "work_items": items,
                       "unit": "face Gauss points" if k == 1 else "fine cells"}
     d = mesh.dim
-    rb = RECON_BYTES_PER_CELL[d]
+    hyb = mesh.cell_offsets is not None
+    rb = RECON_BYTES_PER_CELL["3h" if hyb else d]
     rec = kern["recon"]
     gbs = rb * rec["work_items"] / (rec["avg_ms"] / 1e3) / 1e9
-    rname = f"k_recon<{d}, {shapes[0]}>"     # the autotuned cells per block
+    hy = "true" if hyb else "false"
+    rname = f"k_recon<{d}, {16 if hyb else shapes[0]}, {hy}>"     # the autotuned cells per block
     roof = {"bound": "hbm", "kernel": rname, "achieved": gbs, "peak": MI355X_HBM_GBS, "unit": "GB/s",
             "frac": gbs / MI355X_HBM_GBS, "traffic": TRAFFIC_BYTES.get((args.workload, rname)),
             "avg_ms": rec["avg_ms"], "work_items": rec["work_items"], "bytes_per_item": rb}
     # the flux kernel against the FP64 vector peak, from its counted operations
     fx = kern["flux"]
-    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}, true>"))
+    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}, true, {hy}>"))
     if ops:
         tf = ops * fx["work_items"] / (fx["avg_ms"] / 1e3) / 1e12
         kern["flux"]["fp64"] = {"bound": "fp64", "achieved": tf, "peak": MI355X_FP64_VECTOR_TFLOPS,

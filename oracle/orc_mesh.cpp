@@ -609,6 +609,7 @@ void build_recon_ops(orc_ctx* c) {
     const int dim = c->dim;
     const Level& L0 = c->lv[0];
     c->rop.assign(L0.n, ReconOp());
+#pragma omp parallel for schedule(dynamic, 256)
     for (int i = 0; i < L0.n; ++i) {
         ReconOp& op = c->rop[i];
         for (int fi : L0.cf[i]) {

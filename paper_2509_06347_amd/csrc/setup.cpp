@@ -276,6 +276,29 @@ void for_each_cone(const cgks_ctx* c, const HLevel& L, int i, Fn fn) {
         }
 }
 
+/* Averages over hybrid cell j of the 9 scaled monomials about (xc, h), in
+ * one pass over the symmetric 4-point rule of each of its tetrahedra. */
+void hybrid_basis_averages(const cgks_ctx* c, const HLevel& L, int j, const double* xc, double h, double* out) {
+    const double al = 0.5854101966249685, be = 0.1381966011250105;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, vol = 0.0;
+    for_each_cone(c, L, j, [&](const double* P, double v) {
+        double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 4; ++a) {
+            double X[3];
+            for (int d = 0; d < 3; ++d) {
+                double x = 0.0;
+                for (int q = 0; q < 4; ++q) x += (q == a ? al : be) * P[q * 3 + d];
+                X[d] = (x - xc[d]) / h;
+            }
+            const double phi[9] = {X[0], X[1], X[2], X[0] * X[0], X[0] * X[1], X[0] * X[2], X[1] * X[1], X[1] * X[2], X[2] * X[2]};
+            for (int k = 0; k < 9; ++k) s[k] += phi[k];
+        }
+        for (int k = 0; k < 9; ++k) acc[k] += v * (0.25 * s[k]);
+        vol += v;
+    });
+    for (int k = 0; k < 9; ++k) out[k] = acc[k] / vol;
+}
+
 /* Cell average of f over fine cell i (exact for quadratics). */
 template <class Fn>
 double cell_average(const cgks_ctx* c, const HLevel& L, int i, Fn f) {
@@ -362,8 +385,17 @@ void build_operator(cgks_ctx* c, int i) {
     const int nq = (dim == 2) ? 5 : 9, nslot = (int)L.cf[i].size(), ncol = L.nslot * (1 + dim);
     const double* xc = &L.C[i * dim];
     const double h = L.h[i];
-    for (int k = 0; k < nq; ++k)
-        L.mean0[(size_t)k * L.n + i] = cell_average(c, L, i, [&](const double* x) { return mono(dim, k, x, xc, h); });
+    /* averages of the scaled monomials about (xc, h) over cell j */
+    auto averages = [&](int j, double* out) {
+        if (c->hybrid) {
+            hybrid_basis_averages(c, L, j, xc, h, out);
+            return;
+        }
+        for (int k = 0; k < nq; ++k) out[k] = cell_average(c, L, j, [&](const double* x) { return mono(dim, k, x, xc, h); });
+    };
+    double own[9];
+    averages(i, own);
+    for (int k = 0; k < nq; ++k) L.mean0[(size_t)k * L.n + i] = own[k];
     std::vector<int> slots, nbrs;
     for (int s = 0; s < nslot; ++s) {
         const HFace& f = L.faces[L.cf[i][s]];
@@ -372,6 +404,8 @@ void build_operator(cgks_ctx* c, int i) {
         nbrs.push_back(f.L == i ? f.R : f.L);
     }
     const int nn = (int)nbrs.size();
+    std::vector<double> navg((size_t)nn * nq);
+    for (int m = 0; m < nn; ++m) averages(nbrs[m], &navg[(size_t)m * nq]);
     int nb = 0;
     if (nn * (1 + dim) >= nq) nb = nq;
     else if (nn * (1 + dim) >= dim) nb = dim;
@@ -386,8 +420,7 @@ void build_operator(cgks_ctx* c, int i) {
             for (int d = 0; d < dim; ++d) r2 += (xj[d] - xc[d]) * (xj[d] - xc[d]);
             w[m] = std::sqrt(r2);
             for (int k = 0; k < nb; ++k) {
-                double avg = cell_average(c, L, j, [&](const double* x) { return mono(dim, k, x, xc, h); });
-                E[m * nb + k] = avg - L.mean0[(size_t)k * L.n + i];
+                E[m * nb + k] = navg[(size_t)m * nq + k] - L.mean0[(size_t)k * L.n + i];
                 for (int d = 0; d < dim; ++d) A[(m * dim + d) * nb + k] = w[m] * mono_dx(dim, k, d, xj, xc, h);
             }
         }

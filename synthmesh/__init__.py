@@ -576,44 +576,51 @@ def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tag
     gx, gy, gz = axis(), axis(), axis()
     prism_col = rng.random((n, n)) < p_prism
     pyr_pair = rng.random((n, n, n // 2)) < p_pyramid
+    # nodes: grid nodes (i, j, k) with k fastest, then one centre node per pyramid cube
     X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
-    ijk = [(i, j, k) for i in range(n + 1) for j in range(n + 1) for k in range(n + 1)]
-    unit = [np.array([X[t], Y[t], Z[t]]) for t in ijk]       # before the frustum map
-    nidx = {t: m for m, t in enumerate(ijk)}
-    cells, sides = [], []
-
-    def centre_node(i, j, k):
-        unit.append(np.array([0.5 * (gx[i] + gx[i + 1]), 0.5 * (gy[j] + gy[j + 1]), 0.5 * (gz[k] + gz[k + 1])]))
-        return len(unit) - 1
-
-    cube_of = []
-    for bk in range(n // 2):
-        for bj in range(n // 2):
-            for bi in range(n // 2):
-                for c in range(8):
-                    i, j, k = 2 * bi + (c & 1), 2 * bj + ((c >> 1) & 1), 2 * bk + ((c >> 2) & 1)
-                    v = [nidx[(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1))] for a in range(8)]
-                    bot, top = [v[0], v[1], v[3], v[2]], [v[4], v[5], v[7], v[6]]
-                    cube = (bk * (n // 2) + bj) * (n // 2) + bi
-                    cube = cube * 8 + c
-                    if prism_col[i, j]:
-                        new = [[v[0], v[1], v[3], v[4], v[5], v[7]], [v[0], v[3], v[2], v[4], v[7], v[6]]]
-                    elif pyr_pair[i, j, k // 2]:
-                        cn = centre_node(i, j, k)
-                        quads = [bot, top, [v[0], v[1], v[5], v[4]], [v[1], v[3], v[7], v[5]],
-                                 [v[3], v[2], v[6], v[7]], [v[2], v[0], v[4], v[6]]]
-                        shared = 1 if k % 2 == 0 else 0     # the face towards the pair's other cube
-                        new = []
-                        for f, q in enumerate(quads):
-                            if f == shared:
-                                new += [[q[0], q[1], q[2], cn], [q[0], q[2], q[3], cn]]
-                            else:
-                                new.append(q + [cn])
-                    else:
-                        new = [bot + top]
-                    cells += new
-                    cube_of += [cube] * len(new)
-    unit = np.array(unit)
+    unit = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    n1 = n + 1
+    # cubes in block order (2 x 2 x 2 blocks, block-major), corners a = (a&1, a>>1&1, a>>2&1)
+    bk, bj, bi, c = np.meshgrid(np.arange(n // 2), np.arange(n // 2), np.arange(n // 2), np.arange(8),
+                                indexing="ij")
+    ci = (2 * bi + (c & 1)).ravel()
+    cj = (2 * bj + ((c >> 1) & 1)).ravel()
+    ck = (2 * bk + ((c >> 2) & 1)).ravel()
+    a = np.arange(8)
+    v = ((ci[:, None] + (a & 1)) * n1 + cj[:, None] + ((a >> 1) & 1)) * n1 + ck[:, None] + ((a >> 2) & 1)
+    is_prism = prism_col[ci, cj]
+    is_pyr = ~is_prism & pyr_pair[ci, cj, ck // 2]
+    ncube = len(ci)
+    cube_ids = np.arange(ncube)
+    groups = []    # (cube index, local index, node array [m, nn])
+    hexc = ~is_prism & ~is_pyr
+    groups.append((cube_ids[hexc], 0, v[hexc][:, [0, 1, 3, 2, 4, 5, 7, 6]]))
+    groups.append((cube_ids[is_prism], 0, v[is_prism][:, [0, 1, 3, 4, 5, 7]]))
+    groups.append((cube_ids[is_prism], 1, v[is_prism][:, [0, 3, 2, 4, 7, 6]]))
+    pc = cube_ids[is_pyr]
+    cn = len(unit) + np.arange(len(pc))
+    centres = np.stack([0.5 * (gx[ci[pc]] + gx[ci[pc] + 1]), 0.5 * (gy[cj[pc]] + gy[cj[pc] + 1]),
+                        0.5 * (gz[ck[pc]] + gz[ck[pc] + 1])], axis=1)
+    unit = np.concatenate([unit, centres])
+    quads = [[0, 1, 3, 2], [4, 5, 7, 6], [0, 1, 5, 4], [1, 3, 7, 5], [3, 2, 6, 7], [2, 0, 4, 6]]
+    vp = v[pc]
+    shared = np.where(ck[pc] % 2 == 0, 1, 0)       # the face towards the pair's other cube
+    for f, q in enumerate(quads):
+        qn = vp[:, q]
+        keep = shared != f
+        groups.append((pc[keep], 2 * f, np.concatenate([qn[keep], cn[keep, None]], axis=1)))
+        cut = ~keep
+        groups.append((pc[cut], 2 * f, np.concatenate([qn[cut][:, [0, 1, 2]], cn[cut, None]], axis=1)))
+        groups.append((pc[cut], 2 * f + 1, np.concatenate([qn[cut][:, [0, 2, 3]], cn[cut, None]], axis=1)))
+    cube_all = np.concatenate([g[0] for g in groups])
+    local_all = np.concatenate([np.full(len(g[0]), g[1]) for g in groups])
+    order = np.lexsort((local_all, cube_all))
+    lens = np.concatenate([np.full(len(g[0]), g[2].shape[1]) for g in groups])
+    flat = np.concatenate([g[2].ravel() for g in groups])
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    coff = np.concatenate([[0], np.cumsum(lens[order])]).astype(np.int32)
+    cells_flat = flat[np.repeat(starts[order] - coff[:-1], lens[order]) + np.arange(coff[-1])]
+    cube_of = cube_all[order]
     s = 1.0 + taper * unit[:, 2]
     xyz = np.stack([(unit[:, 0] - 0.5) * s + 0.5, (unit[:, 1] - 0.5) * s + 0.5, unit[:, 2]], axis=1)
     # boundary faces: cell faces that occur once (local face tables of the node orders)
@@ -621,18 +628,26 @@ def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tag
             5: [(0, 1, 2, 3), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)],
             6: [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
             8: [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]}
-    count = {}
-    for cell in cells:
-        for f in ftab[len(cell)]:
-            key = tuple(sorted(cell[a] for a in f))
-            count[key] = count.get(key, (0, [cell[a] for a in f]))
-            count[key] = (count[key][0] + 1, count[key][1])
+    faces = []
+    for g in groups:
+        for f in ftab[g[2].shape[1]]:
+            fa = np.full((len(g[0]), 4), -1, dtype=np.int64)
+            fa[:, :len(f)] = g[2][:, list(f)]
+            faces.append(fa)
+    faces = np.concatenate(faces)
+    key = np.sort(faces, axis=1) + 1                 # node ids + 1 (0 pads a triangle)
+    hi, lo = key[:, 0] << 32 | key[:, 1], key[:, 2] << 32 | key[:, 3]
+    srt = np.lexsort((lo, hi))
+    hs, ls = hi[srt], lo[srt]
+    new_key = np.concatenate([[True], (hs[1:] != hs[:-1]) | (ls[1:] != ls[:-1])])
+    grp = np.cumsum(new_key) - 1
+    count = np.bincount(grp)
+    once = srt[new_key][count == 1]                  # faces used by one cell, in key order
     bfaces, btags = [], []
     tol = 1e-12
-    for key, (cnt, nodes) in count.items():
-        if cnt != 1:
-            continue
-        u = unit[list(nodes)]
+    for row in faces[once]:
+        nodes = [int(v) for v in row if v >= 0]
+        u = unit[nodes]
         for d, ax in enumerate("xyz"):
             if np.all(np.abs(u[:, d]) < tol):
                 btags.append(side_tag[ax + "0"])
@@ -643,11 +658,10 @@ def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tag
         else:
             raise ValueError("boundary face off the box")
         bfaces.append(nodes)
-    coff = np.concatenate([[0], np.cumsum([len(c) for c in cells])]).astype(np.int32)
     boff = np.concatenate([[0], np.cumsum([len(f) for f in bfaces])]).astype(np.int32)
-    parents = [np.array(cube_of, dtype=np.int32), (np.arange(n ** 3, dtype=np.int32) // 8)]
+    parents = [cube_of.astype(np.int32), (np.arange(n ** 3, dtype=np.int32) // 8)]
     kinds = np.bincount(np.diff(coff), minlength=9)
-    return Mesh(3, np.ascontiguousarray(xyz), np.array([v for c in cells for v in c], dtype=np.int32),
+    return Mesh(3, np.ascontiguousarray(xyz), cells_flat.astype(np.int32),
                 np.array([v for f in bfaces for v in f], dtype=np.int32), np.array(btags, dtype=np.int32),
                 parents, dict(kind="hybrid_box", n=n, seed=seed, grade=grade, taper=taper,
                               tets=int(kinds[4]), pyramids=int(kinds[5]), prisms=int(kinds[6]),
