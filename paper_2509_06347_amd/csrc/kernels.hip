@@ -107,6 +107,7 @@ struct Shape {
     static constexpr int NS = HY ? 6 : D + 1;       /* face slots per cell */
     static constexpr int NQ = (D == 2) ? 5 : 9;     /* quadratic basis size */
     static constexpr int NG = HY ? 4 : (D == 2) ? 2 : 3;   /* Gauss points per face */
+    static constexpr int TPF = HY ? 2 : NG;         /* reconstruction threads per face slot */
     static constexpr int NC = NV * (1 + D);         /* state + gradient per Gauss point */
     static constexpr int NCOL = NS * (1 + D);       /* operator inputs */
     static constexpr int NK = NQ + D;               /* coefficients per component: p^2 part, Green-Gauss part */
@@ -228,12 +229,13 @@ struct RLds {
  * five). */
 constexpr int RTHREADS = 384;  /* most threads per reconstruction block: 64 cells in 2-D, 32 in 3-D */
 template <int D, int CELLS, bool HY>
-__global__ void __launch_bounds__((CELLS * Shape<D, HY>::NS * Shape<D, HY>::NG)) __attribute__((amdgpu_waves_per_eu(HY ? 4 : 6)))
+__global__ void __launch_bounds__((CELLS * Shape<D, HY>::NS * Shape<D, HY>::TPF)) __attribute__((amdgpu_waves_per_eu(HY ? 5 : 6)))
 k_recon(FineDev f, KParams kp0) {
     using S = Shape<D, HY>;
     using L = RLds<D, HY>;
     constexpr int NV = S::NV, NS = S::NS, NQ = S::NQ, NG = S::NG, NCOL = S::NCOL, NK = S::NK;
-    constexpr int cells = CELLS, nt = CELLS * NS * NG, cs = CELLS + 1;   /* compile-time: index math by shifts */
+    constexpr int TPF = S::TPF;
+    constexpr int cells = CELLS, nt = CELLS * NS * TPF, cs = CELLS + 1;   /* compile-time: index math by shifts */
     static_assert(nt <= RTHREADS, "reconstruction block");
     extern __shared__ double lds[];
     int* nbf = reinterpret_cast<int*>(lds + (size_t)L::FIELDS * cs);   /* [NS][cells] neighbour, < 0 on boundaries */
@@ -245,10 +247,11 @@ k_recon(FineDev f, KParams kp0) {
 #define FLD(field, cl) lds[(field) * cs + (cl)]
 
     /* ---- 1: loads, (cell, slot, component).  A thread takes at most
-     * ceil(NV / NG) = 2 items and issues all their loads before the first
-     * LDS store, so that the block waits on memory twice, not four times. ---- */
+     * ceil(NV / TPF) items (2; hybrid cells 3) and issues all their loads
+     * before the first LDS store, so that the block waits on memory twice,
+     * not four times. ---- */
     {
-        constexpr int NIT = (NV + NG - 1) / NG;
+        constexpr int NIT = (NV + TPF - 1) / TPF;
         const int total = cells * NS * NV;
         int cl[NIT], sl[NIT], qq[NIT], nb[NIT];
         bool ok[NIT];
@@ -438,9 +441,9 @@ k_recon(FineDev f, KParams kp0) {
     }
     __syncthreads();
 
-    /* ---- 4: positivity guard, (cell, slot, Gauss point).  Triangles: slot
-     * fastest; tetrahedra: cell fastest (slot-fastest lanes measured 1.8x
-     * slower). ---- */
+    /* ---- 4: positivity guard, (cell, slot, Gauss point; hybrid cells: two
+     * points per thread).  Triangles: slot fastest; 3-D: cell fastest
+     * (slot-fastest lanes measured 1.8x slower). ---- */
     {
         int s, cl, k;
         if constexpr (D == 2) {
@@ -449,10 +452,11 @@ k_recon(FineDev f, KParams kp0) {
             k = t / (NS * cells);
         } else {
             cl = t % cells;
-            s = (t / cells) / NG;
-            k = (t / cells) - s * NG;
+            s = (t / cells) / TPF;
+            k = (t / cells) - s * TPF;
         }
         const int i = i0 + cl;
+        auto guard_point = [&](int k) {
         if (i < n && k < NG && active(f.pact, f.pid, i)) {
             double X[3], phi[NQ], dphi[NQ][3], Wx[NV];
 #pragma unroll
@@ -477,6 +481,9 @@ k_recon(FineDev f, KParams kp0) {
             primitive<D>(kp, Wx, P);
             if (!(P.rho > 0.0 && P.p > 0.0)) atomicOr(&bad[cl], 1);
         }
+        };
+        guard_point(k);
+        if constexpr (TPF < NG) guard_point(k + TPF);   /* hybrid cells: two Gauss points per thread */
     }
     __syncthreads();
     for (int u = t; u < cells; u += nt)
@@ -1327,14 +1334,15 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
     FineDev& f = c->fine;
     hipStream_t st = c->stream;
     if (which == 0) {
-        /* block = cells per block x faces x Gauss points (hybrid: 16 cells) */
+        /* block = cells per block x face slots x threads per slot */
         using S = Shape<D, HY>;
-        const int want = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::NG));
-        const int cells = (want <= 16 || HY) ? 16 : (want <= 32 || D == 3 ? 32 : 64);
-        const dim3 grid(blocks(f.n, cells)), blk(cells * S::NS * S::NG);
+        const int want = std::min(block ? block : c->blk_recon, RTHREADS / (S::NS * S::TPF));
+        const int cells = want <= 16 ? 16 : (want <= 32 || D == 3 ? 32 : 64);
+        const dim3 grid(blocks(f.n, cells)), blk(cells * S::NS * S::TPF);
         const size_t lds = RLds<D, HY>::bytes(cells);
         if constexpr (HY) {
-            k_recon<D, 16, true><<<grid, blk, lds, st>>>(f, c->kp);
+            if (cells == 16) k_recon<D, 16, true><<<grid, blk, lds, st>>>(f, c->kp);
+            else k_recon<D, 32, true><<<grid, blk, lds, st>>>(f, c->kp);
         } else {
             if (cells == 16) k_recon<D, 16, false><<<grid, blk, lds, st>>>(f, c->kp);
             else if (cells == 32) k_recon<D, 32, false><<<grid, blk, lds, st>>>(f, c->kp);
