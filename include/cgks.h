@@ -268,7 +268,8 @@ int cgks_run_cycles(cgks_ctx* c, int n, double* history);
  * repetitions runs the whole fine residual on the context's stream, with HIP
  * events around the chosen kernel only, so the kernel sees the cache state of
  * a V-cycle.  The state is not modified.  Also returns the number of work
- * items of one launch. */
+ * items of one launch (hybrid meshes: four flux lanes per face, a
+ * triangle's unused fourth included). */
 int cgks_time_kernel(cgks_ctx* c, int kernel, int reps, double* avg_ms, int64_t* work_items);
 
 /* Choose the launch shape (threads per block) of each fine-residual kernel by
