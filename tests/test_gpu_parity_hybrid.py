@@ -125,6 +125,35 @@ def test_vcycle_trajectory_parity_hybrid(cg, orc, case, use_parents):
     np.testing.assert_allclose(ag, ao, rtol=1e-10, atol=1e-12)
 
 
+def test_guard_and_jump_parity_hybrid(cg, orc):
+    """A density and pressure jump across x = 0.5 carried at Mach 2, with
+    random slopes large enough that the positivity guard makes some cells
+    constant: residual (against the largest per-cell sum of |S F|), slopes,
+    DF and the number of guarded cells agree."""
+    mesh, params = CASES["euler_hybrid"][0](), dict(CASES["euler_hybrid"][1], mach=2.0)
+    g, o = _pair(cg, orc, mesh, **params)
+    V, C = o.cell_geometry(0)
+    right = C[:, 0] > 0.5
+    rho = np.where(right, 4.0, 1.0)
+    p = np.where(right, 15.0, 1.0) / 1.4
+    u = np.where(right, 1.0, 2.0)
+    W = np.stack([rho, rho * u, 0.1 * rho, 0.0 * rho, p / 0.4 + 0.5 * rho * (u * u + 0.01)], axis=1)
+    rng = np.random.default_rng(3)
+    h = V ** (1.0 / 3.0)
+    grad = 0.8 * rng.standard_normal((mesh.n_cells, 5, 3)) * np.abs(W)[:, :, None] / h[:, None, None]
+    for s in (g, o):
+        s.set_state(W, grad, np.ones(mesh.n_cells))
+    Rg, gg, ag = g.residual(0)
+    Ro, go, ao = o.residual(0)
+    hits_g, hits_o = g.stats()[0], o.stats()[0]
+    err = np.abs(Rg - Ro).max() / o.flux_scale()
+    print(f"guarded cells: gpu {hits_g}, oracle {hits_o}; residual error {err:.2e} of the flux scale", flush=True)
+    assert hits_g == hits_o and hits_o > 0
+    assert err <= 1e-12
+    np.testing.assert_allclose(gg, go, rtol=0, atol=1e-11 * np.abs(go).max())
+    np.testing.assert_allclose(ag, ao, rtol=1e-10, atol=1e-13)
+
+
 def test_hybrid_mesh_is_refused_by_batches(cg):
     mesh, params = CASES["euler_hybrid"][0](), CASES["euler_hybrid"][1]
     s = cg.Solver(mesh, n_levels=3, **params)
