@@ -80,10 +80,10 @@ TRAFFIC_BYTES = {
 # wave instruction, FMA counted twice) divided by the launch's Gauss points.
 # Valid only for the flux source the counters were taken with.
 FLUX_FP64_OPS_PER_POINT = {
-    # 64 x (ADD 8.7139e7 + MUL 2.2698e8 + 2 FMA 5.9897e8 + TRANS 1.3662e7) / 18,627,840 points
-    ("sphere_euler_mach6_3.1M", "k_flux<3, true, false>"): 5242,
+    # 64 x (ADD 8.5956e7 + MUL 2.2639e8 + 2 FMA 6.0016e8 + TRANS 1.3662e7) / 18,627,840 points
+    ("sphere_euler_mach6_3.1M", "k_flux<3, true, false, false>"): 5244,
     # 64 x (ADD 6.1384e7 + MUL 1.5297e8 + 2 FMA 4.0608e8 + TRANS 9.906e6) / 12,278,676 Gauss-point lanes
-    ("hybrid_box_ns_mach0.5_1.2M", "k_flux<3, true, true>"): 5402,
+    ("hybrid_box_ns_mach0.5_1.2M", "k_flux<3, true, true, true>"): 5402,
 }
 
 
@@ -597,7 +597,8 @@ def main():
             "avg_ms": rec["avg_ms"], "work_items": rec["work_items"], "bytes_per_item": rb}
     # the flux kernel against the FP64 vector peak, from its counted operations
     fx = kern["flux"]
-    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}, true, {hy}>"))
+    visc = "true" if params.get("reynolds", 0.0) > 0.0 else "false"
+    ops = FLUX_FP64_OPS_PER_POINT.get((args.workload, f"k_flux<{d}, true, {hy}, {visc}>"))
     if ops:
         tf = ops * fx["work_items"] / (fx["avg_ms"] / 1e3) / 1e12
         kern["flux"]["fp64"] = {"bound": "fp64", "achieved": tf, "peak": MI355X_FP64_VECTOR_TFLOPS,

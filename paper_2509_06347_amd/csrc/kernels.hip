@@ -547,9 +547,13 @@ __device__ __forceinline__ void eval_poly(const double* __restrict__ rec, const 
  * the face's record [sum wS F, sum wS W(dt), DF product].  STATE = false:
  * the inviscid residual for restriction, which needs no W(dt); without its
  * moments the kernel nearly fits two waves per SIMD, and asking for two
- * (a few registers spill) measured 1.6 % faster per V-cycle. */
+ * (a few registers spill) measured 1.6 % faster per V-cycle.  VISC = false:
+ * Euler flows, without the viscous collision time and the heat-flux
+ * accumulators (31 fewer accumulation registers, fewer spills: 4.5 % per
+ * V-cycle on the Mach 6 sphere); batches always take VISC = true, their
+ * Reynolds numbers being per problem. */
 constexpr int FTHREADS = 256;
-template <int D, bool STATE, bool HY>
+template <int D, bool STATE, bool HY, bool VISC = true>
 __global__ void __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(STATE ? 1 : 2)))
 k_flux(FineDev f, KParams kp0) {
     using S = Shape<D, HY>;
@@ -584,7 +588,7 @@ k_flux(FineDev f, KParams kp0) {
         double dt = f.dt[L];
         if (R >= 0) dt = fmin(dt, f.dt[R]);
         double Fk[NV], Gk[NV];
-        gks_flux<D, STATE>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
+        gks_flux<D, STATE, VISC>(kp, WL, gL, WR, gR, nn, dt, Fk, Gk, &a);
         double ws = f.fS[fc] / NG;
         if constexpr (HY) {   /* per-point weight x area; a weight-0 point leaves the DF product alone */
             ws = f.fw[(size_t)fc * NG + k];
@@ -1356,8 +1360,10 @@ static void fine_kernel(cgks_ctx* c, int which, int block, int mode) {
         /* the residual for restriction uses no slopes (the state at t = dt);
          * inviscid, its flux needs none of their moments */
         const bool lite = (mode & ~FINE_KEEP) == FINE_RESTRICT && !(c->kp.reynolds > 0.0) && !f.pid;
-        if (lite) k_flux<D, false, HY><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
-        else k_flux<D, true, HY><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        const bool visc = c->kp.reynolds > 0.0 || f.pid;   /* batches: per-problem Reynolds numbers */
+        if (lite) k_flux<D, false, HY, false><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        else if (!visc) k_flux<D, true, HY, false><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
+        else k_flux<D, true, HY, true><<<blocks(waves * 64, b), b, 0, st>>>(f, c->kp);
     } else {
         /* the norm partials use a fixed 256-thread block */
         const int m = mode & ~FINE_KEEP;

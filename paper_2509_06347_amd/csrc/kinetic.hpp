@@ -297,7 +297,7 @@ __host__ __device__ __forceinline__ void rot_grad(const double (*e)[3], const do
  *         correction needs, are skipped and G is zero,
  *      alpha  DF factor of this point (Sec. 3.3).
  */
-template <int D, bool STATE = true>
+template <int D, bool STATE = true, bool VISC = true>
 __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const double (*gLc)[D], const double* WRc,
                          const double (*gRc)[D], const double* n, double dt, double* F, double* G,
                          double* alpha) {
@@ -340,7 +340,7 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
     /* collision time (numerical part from the pressure jump) */
     const double jump = fabs(PL.p - PR.p) / (PL.p + PR.p);
     double tau;
-    if (kp.reynolds > 0.0)
+    if (VISC && kp.reynolds > 0.0)
         tau = sutherland(kp, PC.p / PC.rho) / PC.p + kp.tau_c2 * jump * dt;
     else
         tau = kp.tau_c1 * dt + kp.tau_c2 * jump * dt;
@@ -414,7 +414,7 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 Gl[q] += P.rho * (ex * t[q] - (dt + tau) * ex * t2[q] - tau * ex * tA[q]);
-                Wf[q] += P.rho * (q4 * t[q] - q5 * t2[q] - q6 * tA[q]);
+                if constexpr (VISC) Wf[q] += P.rho * (q4 * t[q] - q5 * t2[q] - q6 * tA[q]);
             }
         }
     }
@@ -449,14 +449,14 @@ __host__ __device__ void gks_flux(const KParams& kp, const double* WLc, const do
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 Gl[q] += PC.rho * (C1 * tp[q] + C2 * t2[q] + C3 * tA[q]);
-                Wf[q] += PC.rho * (q1 * tp[q] + q2 * t2[q] + q3 * tA[q]);
+                if constexpr (VISC) Wf[q] += PC.rho * (q1 * tp[q] + q2 * t2[q] + q3 * tA[q]);
             }
         }
     }
     const double idt = 1.0 / dt;
 #pragma unroll
     for (int q = 0; q < NV; ++q) Fl[q] *= idt;
-    if (STATE && kp.reynolds > 0.0) {
+    if (STATE && VISC && kp.reynolds > 0.0) {
         /* BGK heat flux 1/2 <(u-U)(|u-U|^2+xi^2) f> from flux and conserved moments */
         double u2 = 0.0, UF = 0.0, UW = 0.0;
 #pragma unroll
