@@ -33,6 +33,9 @@ CASES = {
                             dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
     "ns_hybrid_isothermal": (lambda: sm.hybrid_box(8, seed=3, tags={"z0": sm.ISOTHERMAL}),
                              dict(dim=3, mach=0.5, aoa_deg=10.0, reynolds=100.0)),
+    # 414 cells: the last reconstruction block of 16 cells is partial (14 cells)
+    "euler_hybrid_ragged": (lambda: sm.hybrid_box(6, seed=4, tags={"z0": sm.SLIP}),
+                            dict(dim=3, mach=0.5, aoa_deg=10.0)),
 }
 
 
@@ -107,7 +110,7 @@ def test_fine_residual_parity_hybrid(cg, orc, case):
 
 
 @pytest.mark.parametrize("case,use_parents", [("euler_hybrid", True), ("ns_hybrid_adiabatic", True),
-                                              ("ns_hybrid_isothermal", False)])
+                                              ("ns_hybrid_isothermal", False), ("euler_hybrid_ragged", True)])
 def test_vcycle_trajectory_parity_hybrid(cg, orc, case, use_parents):
     mesh, params = CASES[case][0](), CASES[case][1]
     g, o = _pair(cg, orc, mesh, use_parents=use_parents, **params)
