@@ -342,6 +342,20 @@ int upload(cgks_ctx* c) {
     TRY(dalloc(c, &f.gsave, (size_t)nv * dim * n));
     TRY(dalloc(c, &f.asave, n));
     TRY(dalloc(c, &f.poly, (size_t)(dim == 2 ? 40 : 80) * n));
+    {
+        /* the records' static part, written once: basis means, centroid and
+         * 1/h after the coefficients [nv][nq + dim] and the cell averages [nv]
+         * (the reconstruction writes only those two) */
+        const int npr = dim == 2 ? 40 : 80, rmean = nv * (nq + dim) + nv, rcen = rmean + nq, rih = rcen + dim;
+        std::vector<double> rec((size_t)npr * n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            double* r = &rec[(size_t)i * npr];
+            for (int m = 0; m < nq; ++m) r[rmean + m] = H.mean0[(size_t)m * n + i];
+            for (int d = 0; d < dim; ++d) r[rcen + d] = H.C[(size_t)i * dim + d];
+            r[rih] = 1.0 / H.h[i];
+        }
+        TRY(h2d(c, f.poly, rec));
+    }
     TRY(dalloc(c, &f.fX, (size_t)nf * ng * dim)); TRY(h2d(c, f.fX, fX));
     if (c->hybrid) {
         TRY(dalloc(c, &f.fw, (size_t)nf * ng));

@@ -488,18 +488,15 @@ k_recon(FineDev f, KParams kp0) {
     __syncthreads();
     for (int u = t; u < cells; u += nt)
         if (i0 + u < n && bad[u] && active(f.pact, f.pid, i0 + u)) atomicAdd(f.guard, 1ull);
-    /* the cells' polynomial records, written contiguously by the whole block */
-    constexpr int NPR = S::NPR;
+    /* the cells' polynomial records, written contiguously by the whole block:
+     * coefficients and cell averages (the static rest, basis means,
+     * centroid and 1/h, is written once when the mesh is uploaded) */
+    constexpr int NPR = S::NPR, NDYN = S::REC_MEAN;
     const int ncell = min(cells, n - i0);
-    for (int e = t; e < ncell * NPR; e += nt) {
-        const int c2 = e / NPR, jj = e - c2 * NPR, ii = i0 + c2;
+    for (int e = t; e < ncell * NDYN; e += nt) {
+        const int c2 = e / NDYN, jj = e - c2 * NDYN, ii = i0 + c2;
         if (!active(f.pact, f.pid, ii)) continue;
-        double v = 0.0;
-        if (jj < S::REC_W) v = bad[c2] ? 0.0 : FLD(L::COEF + jj, c2);
-        else if (jj < S::REC_MEAN) v = FLD(L::W0 + jj - S::REC_W, c2);
-        else if (jj < S::REC_C) v = FLD(L::MEAN + jj - S::REC_MEAN, c2);
-        else if (jj < S::REC_IH) v = f.C[(size_t)(jj - S::REC_C) * n + ii];
-        else if (jj == S::REC_IH) v = 1.0 / FLD(L::CEL + 1, c2);
+        const double v = jj < S::REC_W ? (bad[c2] ? 0.0 : FLD(L::COEF + jj, c2)) : FLD(L::W0 + jj - S::REC_W, c2);
         f.poly[(size_t)ii * NPR + jj] = v;
     }
 #undef FLD
