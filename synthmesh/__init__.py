@@ -557,10 +557,11 @@ def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tag
     p_pyramid, become six pyramids each (apex at a new node at the cube's
     centre), and the two pyramids on the quadrilateral the pair shares are
     cut into two tetrahedra each along the same diagonal; every other cube is
-    a hexahedron.  Cells are numbered cube by cube and cubes block by block
-    of 2 x 2 x 2, so parents[0] maps a cell to its cube and parents[1] a cube
-    to its block.  tags maps a side ('x0', 'x1', 'y0', 'y1', 'z0', 'z1') to
-    its boundary tag (default far field).  Node orders: ELEMENT_ORDER."""
+    a hexahedron.  Cells are numbered cube by cube and cubes in Morton order,
+    so that the 8 cubes of each 2 x 2 x 2 block are consecutive: parents[0]
+    maps a cell to its cube and parents[1] a cube to its block.  tags maps
+    a side ('x0', 'x1', 'y0', 'y1', 'z0', 'z1') to its boundary tag
+    (default far field).  Node orders: ELEMENT_ORDER."""
     if n % 2:
         raise ValueError("n must be even")
     rng = np.random.default_rng(seed)
@@ -580,12 +581,16 @@ def hybrid_box(n, seed=0, grade=0.3, taper=0.3, p_prism=0.3, p_pyramid=0.25, tag
     X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
     unit = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
     n1 = n + 1
-    # cubes in block order (2 x 2 x 2 blocks, block-major), corners a = (a&1, a>>1&1, a>>2&1)
-    bk, bj, bi, c = np.meshgrid(np.arange(n // 2), np.arange(n // 2), np.arange(n // 2), np.arange(8),
-                                indexing="ij")
-    ci = (2 * bi + (c & 1)).ravel()
-    cj = (2 * bj + ((c >> 1) & 1)).ravel()
-    ck = (2 * bk + ((c >> 2) & 1)).ravel()
+    # cubes in Morton (bit-interleaved) order of (i, j, k): the 8 cubes of a
+    # 2 x 2 x 2 block stay consecutive, and so do larger blocks, which keeps
+    # most face neighbours close in the numbering; corners a = (a&1, a>>1&1, a>>2&1)
+    I, J, K = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    code = np.zeros(n ** 3, dtype=np.int64)
+    for b in range(int(np.ceil(np.log2(n))) + 1):
+        code |= ((I >> b) & 1) << (3 * b) | ((J >> b) & 1) << (3 * b + 1) | ((K >> b) & 1) << (3 * b + 2)
+    morton = np.argsort(code, kind="stable")
+    ci, cj, ck = I[morton], J[morton], K[morton]
     a = np.arange(8)
     v = ((ci[:, None] + (a & 1)) * n1 + cj[:, None] + ((a >> 1) & 1)) * n1 + ck[:, None] + ((a >> 2) & 1)
     is_prism = prism_col[ci, cj]
